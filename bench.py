@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the FP64 FMM gravity solve, forward + adjoint, at 128^3.
+
+One step = one forward (rho -> phi, g) and one adjoint ((dphi, dg) -> drho)
+of the whole 128^3 two-polytrope workload (uniform octree of depth 4, 4096
+leaf sub-grids of 8^3 cells, theta = 0.4, order 3), inputs resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--cpu-slab Z]
+
+Prints one JSON line.  `value` counts evaluated ordered cell pairs (leaf P2P
+pairs plus M2L pairs of the coarser levels) per second over the K timed steps.
+`roofline` reports the kernel with the largest share of the timed region,
+against the FP64 vector peak of the MI355X.  `cpu_baseline` times the CPU
+oracle (forward + adjoint) on a z-slab of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12       # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
+METRIC = "cell-interactions/s & FP64 FLOP/s (fwd+adjoint) at 128³ vs FP64 peak; oracle err"
+KERNEL_OF_PHASE = {"m2l": "k_m2l", "leaf": "k_leaf<false>", "leaf_adj": "k_leaf<true>",
+                   "upward_leaf": "k_upward_leaf<false>", "upward_leaf_adj": "k_upward_leaf<true>",
+                   "m2m": "k_m2m", "l2l": "k_l2l"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ot_fmm_kernels.hip", "ot_fmm_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2412_15518_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(phase: str):
+    """HBM traffic per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{phase}_traffic_128.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def phase_flops(phase: str, info: dict) -> float:
+    N = info["n_leaf_cells"]
+    L = info["depth"]
+    inner = sum((8 << l) ** 3 for l in range(1, L))
+    return {"m2l": 168.0 * info["m2l_pairs"],
+            "leaf": 8.0 * info["p2p_pairs"] + 100.0 * N,
+            "leaf_adj": 8.0 * info["p2p_pairs"] + 40.0 * N,
+            "upward_leaf": 40.0 * N,
+            "upward_leaf_adj": 100.0 * N,
+            "m2m": 168.0 * inner,
+            "l2l": 168.0 * inner}[phase]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-slab", type=int, default=16,
+                    help="leaf z-layers of the 128^3 grid in the CPU-oracle sample (0: skip)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2412_15518_amd import fmm, workloads as W
+
+    torch.cuda.set_device(0)
+    log("generating the 128^3 two-polytrope workload")
+    cfg = W.cfg2_two_polytropes()
+    lay = W.uniform_layout(cfg["L"])
+    plan = fmm.Plan(lay, theta=0.4, order=3)
+    info = plan.info()
+    N = info["n_leaf_cells"]
+    dev = lambda a: torch.from_numpy(lay.dense_to_layout(a)).cuda()   # noqa: E731
+    rho, w, u = dev(cfg["rho"]), dev(cfg["w"]), dev(cfg["u"])
+    phi = torch.empty(N, dtype=torch.float64, device="cuda")
+    g = torch.empty((3, N), dtype=torch.float64, device="cuda")
+    drho = torch.empty(N, dtype=torch.float64, device="cuda")
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        plan.forward_into(rho, phi, g)
+        plan.adjoint_into(w, u.reshape(-1), drho)
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    plan.timing_begin(2 * args.steps)
+    torch.cuda.synchronize()            # (one rank: the barrier is this synchronisation)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.forward_into(rho, phi, g)
+        plan.adjoint_into(w, u.reshape(-1), drho)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = plan.timing_end()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    pairs_step = 2 * (info["p2p_pairs"] + info["m2l_pairs"])
+    flops_step = info["flops_forward"] + info["flops_adjoint"]
+    value = pairs_step * args.steps / elapsed
+    fp64 = flops_step * args.steps / elapsed
+
+    phases = {k: v for k, v in tim["phases"].items() if k != "total" and v["launches"] > 0}
+    dom = max(phases, key=lambda k: phases[k]["ms"])
+    d = phases[dom]
+    avg_ms = d["ms"] / d["events"]
+    fl_launch = phase_flops(dom, info)
+    achieved = fl_launch / (avg_ms * 1e-3) / 1e12
+    traffic = read_traffic(dom)
+    per_phase = {k: {"avg_ms": v["ms"] / v["events"], "share": v["ms"] / (1e3 * elapsed),
+                     "tflops": phase_flops(k, info) * v["launches"] / v["events"] / (v["ms"] / v["events"] * 1e-3) / 1e12
+                     if k not in ("m2m", "l2l") else None}
+                 for k, v in phases.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "two n=1.5 polytropes (rho_c 1.0/0.6, R 20/14 cells, 50 apart) + 1e-10 floor, "
+                               "+-1% noise; uniform octree depth 4 = 128^3 cells in 4096 sub-grids of 8^3; "
+                               "theta 0.4, order 3; one step = forward + adjoint",
+                   "grid": 128, "depth": 4, "theta": 0.4, "order": 3,
+                   "cell_interactions_per_step": pairs_step, "fp64_flop_per_step": flops_step},
+        "fp64_flops_per_s": fp64,
+        "frac_fp64_peak": fp64 / PEAK_FP64,
+        "roofline": {"bound": "alu", "kernel": KERNEL_OF_PHASE[dom], "achieved": achieved,
+                     "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64 / 1e12),
+                     "traffic": traffic, "avg_launch_ms": avg_ms, "flop_per_launch": fl_launch},
+        "phases": per_phase,
+    }
+
+    if args.cpu_slab > 0:
+        import oracle as O
+        z0 = 64 - args.cpu_slab // 2
+        z1 = z0 + args.cpu_slab
+        p2p, m2l = O.pair_counts(cfg["L"], 0.4, zslab=(z0, z1))
+        sample_pairs = p2p + int(m2l.sum())
+        log(f"CPU oracle on leaf z-slab [{z0},{z1}) with {O.threads()} threads")
+        c0 = time.perf_counter()
+        po, go = O.fmm(cfg["rho"], zslab=(z0, z1))
+        c1 = time.perf_counter()
+        do = O.fmm_adjoint(cfg["w"], cfg["u"], zslab=(z0, z1))
+        c2 = time.perf_counter()
+        out["cpu_baseline"] = {"value": 2 * sample_pairs / (c2 - c0), "unit": "cell-interactions/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"forward + adjoint of the same 128^3 workload, sinks restricted to leaf "
+                                         f"z-slab [{z0},{z1}) ({2 * sample_pairs:.4g} cell-interactions, "
+                                         f"{c2 - c0:.1f} s)"}
+        ph = lay.layout_to_dense(phi.cpu().numpy())[z0:z1]
+        gg = lay.layout_to_dense(g.cpu().numpy())[:, z0:z1]
+        dr = lay.layout_to_dense(drho.cpu().numpy())[z0:z1]
+        po, go, do = po[z0:z1], go[:, z0:z1], do[z0:z1]
+        out["oracle_err"] = {
+            "phi": float(np.abs(ph - po).max() / np.abs(po).max()),
+            "g": float(np.sqrt(((gg - go) ** 2).sum(0)).max() / np.sqrt((go ** 2).sum(0)).max()),
+            "drho": float(np.abs(dr - do).max() / np.abs(do).max()),
+            "norm": "normwise max-abs, over the oracle z-slab", "tolerance": 1e-12}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

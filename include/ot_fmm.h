@@ -1,0 +1,162 @@
+/*
+ * ot_fmm.h -- C ABI of the MI355X octree fast-multipole self-gravity library.
+ *
+ * The operation is the gravity solve of Octo-Tiger (arXiv 2412.15518): Sec. 4.3
+ * ("Octo-Tiger in a Nutshell") describes an FMM gravity solver on an octree
+ * whose nodes each hold an 8x8x8-cell sub-grid, and Sec. 5.5 the stencil form
+ * of its same-level interactions.  The paper gives no formulas; this library
+ * implements the following reading of it, with G the gravitational constant
+ * and h the leaf cell width:
+ *
+ *   phi_i = -G sum_{j != i} m_j / |x_i - x_j|,     g_i = -grad phi at x_i,
+ *   m_j = rho_j h^3 at the geometric centre of leaf cell j,
+ *
+ * evaluated by a Cartesian FMM of total order p = 3 with expansions about
+ * geometric cell centres: P2M/M2M moment aggregation, same-level M2L over the
+ * parity-aware stencil (a cell pair of level l >= 1 interacts at l when the
+ * cells are farther apart than 1/theta cell widths and their parents are not;
+ * the root sub-grid takes all its far pairs), exact P2P over every leaf pair
+ * whose parents are near, and L2L/L2P back to the leaf centres.  Domain
+ * boundaries are isolated (no mass outside the tree).
+ *
+ * The adjoint returns d rho of  sum_i dphi_i phi_i + sum_i dg_i . g_i  through
+ * the same discrete operator (its exact transpose).
+ *
+ * Conventions for every entry point:
+ *  - Return 0 (OT_FMM_OK) on success or a negative status; the status string
+ *    and ot_fmm_last_error() (a per-thread message) describe the failure.
+ *    No entry point aborts or prints.
+ *  - Device arrays are caller-owned FP64 device pointers, 8-byte aligned,
+ *    densely packed.  A cell field (rho, phi, dphi, drho) holds
+ *    N = 512 * n_leaf_nodes values: leaf k of the layout (leaves counted in
+ *    node order) owns [512 k, 512 k + 512), x fastest inside the sub-grid.
+ *    Vector fields (g, dg) are three such planes (x, y, z) back to back.
+ *  - Work is enqueued on the given HIP stream (NULL = the default stream) with
+ *    no host synchronisation; results are ready when the stream reaches them.
+ *    A plan owns scratch memory and must not run on two streams at once.
+ *  - Forward and adjoint allocate nothing: the plan allocates all device
+ *    memory at creation.
+ */
+#ifndef OT_FMM_H
+#define OT_FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define OT_FMM_OK                   0
+#define OT_FMM_INVALID_ARGUMENT    -1  /* null/misaligned pointer, bad flag, NaN */
+#define OT_FMM_INVALID_LAYOUT      -2  /* not a proper octree (see plan_create) */
+#define OT_FMM_UNSUPPORTED_ORDER   -3  /* order other than 3 */
+#define OT_FMM_UNSUPPORTED_THETA   -4  /* theta outside (1/3, 1] */
+#define OT_FMM_UNSUPPORTED_LAYOUT  -5  /* valid octree this build cannot run (leaves at several levels, depth > 7) */
+#define OT_FMM_OUT_OF_MEMORY       -6  /* host or device allocation failed */
+#define OT_FMM_DEVICE_ERROR        -7  /* a HIP call failed */
+#define OT_FMM_NO_DEVICE_STATE     -8  /* plan created with OT_FMM_HOST_ONLY */
+
+/* ---- plan flags -------------------------------------------------------- */
+#define OT_FMM_FP64       0u         /* all arithmetic in FP64 (default) */
+#define OT_FMM_HOST_ONLY  (1u << 0)  /* validate and build host tables only: no
+                                        device memory; plan_info works, forward
+                                        and adjoint return OT_FMM_NO_DEVICE_STATE */
+
+typedef struct ot_fmm_plan_s *ot_fmm_plan;   /* opaque */
+
+/* Octree of 8^3-cell sub-grids (paper Sec. 4.3).  Node 0 is the root (level 0,
+ * coord (0,0,0), parent -1).  A node of level l has integer sub-grid
+ * coordinates in [0, 2^l)^3; its parent has level l-1 and coordinates
+ * coord >> 1; a node is either a leaf or has all 8 children.  The leaf cell
+ * width is h_leaf_min; a cell of level l is 2^(L-l) times wider, L being the
+ * deepest level.  origin (the low corner of the root) shifts every position
+ * alike and does not change phi or g.  The arrays are read during
+ * plan_create only. */
+typedef struct {
+    int32_t        n_nodes;
+    const int32_t *level;     /* [n_nodes] */
+    const int32_t *coord;     /* [3 * n_nodes] x, y, z per node */
+    const int32_t *parent;    /* [n_nodes] */
+    const uint8_t *is_leaf;   /* [n_nodes] 0 or 1 */
+    double         h_leaf_min;
+    double         origin[3];
+    double         G;
+} ot_octree_layout;
+
+typedef struct {
+    int32_t depth;                 /* L, leaf level */
+    int32_t order;                 /* expansion order p */
+    double  theta;                 /* opening parameter; near radius 1/theta cells */
+    int64_t n_nodes;
+    int64_t n_leaf_nodes;
+    int64_t n_leaf_cells;          /* 512 * n_leaf_nodes */
+    int64_t p2p_pairs;             /* ordered leaf pairs evaluated exactly (both cells in the domain) */
+    int64_t m2l_pairs;             /* ordered M2L pairs over the levels below the leaves */
+    int64_t m2l_pairs_level[16];   /* per level 0..L-1 */
+    double  flops_forward;         /* algorithmic FP64 FLOP per forward (8 per P2P pair, 168 per M2L pair, plus M2M/L2L) */
+    double  flops_adjoint;         /* same for the adjoint */
+    double  bytes_forward;         /* algorithmic HBM bytes per forward */
+    double  bytes_adjoint;
+    size_t  device_bytes;          /* device memory owned by the plan */
+} ot_fmm_info;
+
+/* Validate `layout`, build the interaction tables and allocate all device
+ * scratch on the current HIP device.  theta in (1/3, 1] (0.4 gives the
+ * near radius of 2.5 cells), order = 3.  On success *out owns the plan; on
+ * failure *out is NULL.  Layout errors (INVALID_LAYOUT): root not node 0, a
+ * parent index out of range or at the wrong level, coordinates outside the
+ * level or not within the parent, duplicate nodes, an internal node without
+ * all 8 children, a leaf with children. */
+int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order,
+                       uint32_t flags, ot_fmm_plan *out);
+
+/* phi[N], g[3N] <- FMM of rho[N] (device pointers, layout order). */
+int ot_fmm_forward(ot_fmm_plan plan, const double *rho, double *phi, double *g,
+                   void *hip_stream);
+
+/* drho[N] <- transpose of the forward operator applied to (dphi[N], dg[3N]). */
+int ot_fmm_adjoint(ot_fmm_plan plan, const double *dphi, const double *dg,
+                   double *drho, void *hip_stream);
+
+int ot_fmm_plan_info(ot_fmm_plan plan, ot_fmm_info *info);
+
+/* Releases the plan and its device memory (the device must be idle for it).
+ * NULL is a no-op. */
+void ot_fmm_destroy(ot_fmm_plan plan);
+
+const char *ot_fmm_status_string(int status);
+const char *ot_fmm_last_error(void);   /* message of this thread's last failure */
+
+/* ---- kernel timing ------------------------------------------------------
+ * Between timing_begin and timing_end every forward/adjoint call records HIP
+ * events on its stream around each kernel phase (at most max_calls calls are
+ * recorded).  timing_end waits for the last event and reports, per phase, the
+ * number of timed launches and their summed duration. */
+#define OT_FMM_PHASE_UPWARD_LEAF      0   /* P2M + first M2M, forward */
+#define OT_FMM_PHASE_M2M              1   /* M2M, levels L-2..0 (all launches of a call) */
+#define OT_FMM_PHASE_M2L              2   /* M2L, all levels, one launch */
+#define OT_FMM_PHASE_L2L              3   /* L2L, levels 1..L-1 (all launches of a call) */
+#define OT_FMM_PHASE_LEAF             4   /* leaf P2P + L2P, forward */
+#define OT_FMM_PHASE_UPWARD_LEAF_ADJ  5
+#define OT_FMM_PHASE_LEAF_ADJ         6
+#define OT_FMM_PHASE_TOTAL            7   /* whole forward or adjoint call */
+#define OT_FMM_NUM_PHASES             8
+
+typedef struct {
+    int32_t calls;                          /* calls recorded */
+    int64_t launches[OT_FMM_NUM_PHASES];    /* kernel launches per phase */
+    int64_t events[OT_FMM_NUM_PHASES];      /* timed intervals per phase */
+    double  ms[OT_FMM_NUM_PHASES];          /* summed interval time per phase */
+} ot_fmm_timing;
+
+int ot_fmm_timing_begin(ot_fmm_plan plan, int max_calls);
+int ot_fmm_timing_end(ot_fmm_plan plan, ot_fmm_timing *out);
+const char *ot_fmm_phase_name(int phase);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OT_FMM_H */

@@ -1,0 +1,687 @@
+// ot_fmm_api.hip -- C ABI, plan construction and call orchestration.
+//
+// plan_create validates the octree, builds the per-level interaction tables
+// (parent-offset lists, the derivative tensors of K = -G/r per stencil offset,
+// the leaf pair kernel K0/K1) and allocates every device buffer once, so that
+// forward and adjoint only enqueue kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "ot_fmm_internal.h"
+
+using namespace otfmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(OT_FMM_DEVICE_ERROR, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// derivative tensor of K(r) = -G/|r| at R = (x, y, z), orders 0..3, in the
+// kernels' component order (0; x y z; xx xy xz yy yz zz; xxx xxy xxz xyy xyz
+// xzz yyy yyz yzz zzz), from the closed forms
+//   d_i (1/r)         = -x_i / r^3
+//   d_i d_j (1/r)     = 3 x_i x_j / r^5 - delta_ij / r^3
+//   d_i d_j d_k (1/r) = -15 x_i x_j x_k / r^7
+//                       + 3 (delta_ij x_k + delta_ik x_j + delta_jk x_i) / r^5
+// ---------------------------------------------------------------------------
+void derivative_tensor(double G, double x, double y, double z, double *D)
+{
+    const double X[3] = {x, y, z};
+    const double r = std::sqrt(x * x + y * y + z * z);
+    const double ir = 1.0 / r, ir2 = ir * ir, ir3 = ir * ir2, ir5 = ir3 * ir2, ir7 = ir5 * ir2;
+    auto dl = [](int i, int j) { return i == j ? 1.0 : 0.0; };
+    D[0] = -G * ir;
+    for (int i = 0; i < 3; ++i) D[1 + i] = G * X[i] * ir3;
+    static const int two[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    for (int c = 0; c < 6; ++c) {
+        const int i = two[c][0], j = two[c][1];
+        D[4 + c] = -G * (3.0 * X[i] * X[j] * ir5 - dl(i, j) * ir3);
+    }
+    static const int three[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
+                                     {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
+    for (int c = 0; c < 10; ++c) {
+        const int i = three[c][0], j = three[c][1], k = three[c][2];
+        const double t = -15.0 * X[i] * X[j] * X[k] * ir7 +
+                         3.0 * (dl(i, j) * X[k] + dl(i, k) * X[j] + dl(j, k) * X[i]) * ir5;
+        D[10 + c] = -G * t;
+    }
+}
+
+// cells c in [0, n) with c = b (mod 2) whose partner c + o is in [0, n)
+int64_t axis_count(int n, int b, int o)
+{
+    int64_t cnt = 0;
+    for (int c = b; c < n; c += 2)
+        if (c + o >= 0 && c + o < n) ++cnt;
+    return cnt;
+}
+
+struct Key {
+    int l, x, y, z;
+    bool operator==(const Key &o) const { return l == o.l && x == o.x && y == o.y && z == o.z; }
+};
+struct KeyHash {
+    size_t operator()(const Key &k) const
+    {
+        uint64_t h = (uint64_t)(uint32_t)k.l * 0x9E3779B97F4A7C15ull;
+        h ^= (uint64_t)(uint32_t)k.x + 0x7F4A7C15ull + (h << 6) + (h >> 2);
+        h ^= (uint64_t)(uint32_t)k.y + 0x9E3779B9ull + (h << 6) + (h >> 2);
+        h ^= (uint64_t)(uint32_t)k.z + 0x85EBCA6Bull + (h << 6) + (h >> 2);
+        return (size_t)h;
+    }
+};
+
+int validate_layout(const ot_octree_layout *lay, ot_fmm_plan P)
+{
+    if (!lay) return fail(OT_FMM_INVALID_ARGUMENT, "layout is NULL");
+    const int64_t n = lay->n_nodes;
+    if (n < 1) return fail(OT_FMM_INVALID_LAYOUT, "layout has no nodes");
+    if (!lay->level || !lay->coord || !lay->parent || !lay->is_leaf)
+        return fail(OT_FMM_INVALID_ARGUMENT, "layout array pointer is NULL");
+    if (!(lay->h_leaf_min > 0.0) || !std::isfinite(lay->h_leaf_min))
+        return fail(OT_FMM_INVALID_ARGUMENT, "h_leaf_min must be finite and > 0");
+    if (!std::isfinite(lay->G)) return fail(OT_FMM_INVALID_ARGUMENT, "G must be finite");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(lay->origin[k])) return fail(OT_FMM_INVALID_ARGUMENT, "origin must be finite");
+    if (lay->level[0] != 0 || lay->parent[0] != -1 || lay->coord[0] || lay->coord[1] || lay->coord[2])
+        return fail(OT_FMM_INVALID_LAYOUT, "node 0 must be the root: level 0, parent -1, coord (0,0,0)");
+
+    std::vector<int> nchild((size_t)n, 0);
+    std::unordered_set<Key, KeyHash> seen;
+    seen.reserve((size_t)n * 2);
+    int L = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int l = lay->level[i];
+        const int x = lay->coord[3 * i], y = lay->coord[3 * i + 1], z = lay->coord[3 * i + 2];
+        char buf[160];
+        if (l < 0 || l > 30) {
+            snprintf(buf, sizeof buf, "node %lld: level %d out of range", (long long)i, l);
+            return fail(OT_FMM_INVALID_LAYOUT, buf);
+        }
+        const int m = 1 << l;
+        if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) {
+            snprintf(buf, sizeof buf, "node %lld: coordinates (%d,%d,%d) outside level %d", (long long)i, x, y, z, l);
+            return fail(OT_FMM_INVALID_LAYOUT, buf);
+        }
+        if (lay->is_leaf[i] > 1) {
+            snprintf(buf, sizeof buf, "node %lld: is_leaf must be 0 or 1", (long long)i);
+            return fail(OT_FMM_INVALID_LAYOUT, buf);
+        }
+        if (i > 0) {
+            const int64_t pa = lay->parent[i];
+            if (pa < 0 || pa >= n || pa == i) {
+                snprintf(buf, sizeof buf, "node %lld: parent %lld out of range", (long long)i, (long long)pa);
+                return fail(OT_FMM_INVALID_LAYOUT, buf);
+            }
+            if (lay->level[pa] != l - 1) {
+                snprintf(buf, sizeof buf, "node %lld: parent %lld is not one level up", (long long)i, (long long)pa);
+                return fail(OT_FMM_INVALID_LAYOUT, buf);
+            }
+            if (lay->coord[3 * pa] != (x >> 1) || lay->coord[3 * pa + 1] != (y >> 1) ||
+                lay->coord[3 * pa + 2] != (z >> 1)) {
+                snprintf(buf, sizeof buf, "node %lld: coordinates not inside parent %lld", (long long)i, (long long)pa);
+                return fail(OT_FMM_INVALID_LAYOUT, buf);
+            }
+            nchild[(size_t)pa] += 1;
+        }
+        if (!seen.insert(Key{l, x, y, z}).second) {
+            snprintf(buf, sizeof buf, "node %lld: duplicate of an earlier node (level %d, %d,%d,%d)",
+                     (long long)i, l, x, y, z);
+            return fail(OT_FMM_INVALID_LAYOUT, buf);
+        }
+        L = std::max(L, l);
+    }
+    int64_t nleaf = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        char buf[128];
+        if (lay->is_leaf[i]) {
+            if (nchild[(size_t)i] != 0) {
+                snprintf(buf, sizeof buf, "node %lld: leaf with children", (long long)i);
+                return fail(OT_FMM_INVALID_LAYOUT, buf);
+            }
+            ++nleaf;
+        } else if (nchild[(size_t)i] != 8) {
+            snprintf(buf, sizeof buf, "node %lld: internal node with %d of 8 children", (long long)i, nchild[(size_t)i]);
+            return fail(OT_FMM_INVALID_LAYOUT, buf);
+        }
+    }
+    if (L > MAX_LEVELS - 1)
+        return fail(OT_FMM_UNSUPPORTED_LAYOUT, "octree deeper than 7 levels");
+    for (int64_t i = 0; i < n; ++i)
+        if (lay->is_leaf[i] && lay->level[i] != L)
+            return fail(OT_FMM_UNSUPPORTED_LAYOUT,
+                        "leaves on several levels (adaptive refinement) are not supported by this build");
+
+    // a valid octree whose leaves all sit at level L is the full tree of depth L
+    P->L = L;
+    P->n_nodes = n;
+    P->n_leaf_nodes = nleaf;
+    const int sL = 1 << L;
+    P->leaf_slot.assign((size_t)sL * sL * sL, -1);
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!lay->is_leaf[i]) continue;
+        const int x = lay->coord[3 * i], y = lay->coord[3 * i + 1], z = lay->coord[3 * i + 2];
+        P->leaf_slot[((size_t)z * sL + y) * sL + x] = (int32_t)k++;
+    }
+    P->h = lay->h_leaf_min;
+    P->G = lay->G;
+    return OT_FMM_OK;
+}
+
+void build_tables(ot_fmm_plan P)
+{
+    const int L = P->L;
+    const double r2 = P->r2;
+    // integer r2i: |o|^2 > r2i  <=>  (double)|o|^2 > r2
+    int r2i = 0;
+    while ((double)(r2i + 1) <= r2) ++r2i;
+    P->dp.r2i = r2i;
+
+    P->plist_near.clear();
+    P->plist_cube.clear();
+    for (int z = -3; z <= 3; ++z)
+        for (int y = -3; y <= 3; ++y)
+            for (int x = -3; x <= 3; ++x) {
+                char4 c;
+                c.x = (signed char)x; c.y = (signed char)y; c.z = (signed char)z; c.w = 0;
+                P->plist_cube.push_back(c);
+                if (x * x + y * y + z * z <= r2i) P->plist_near.push_back(c);
+            }
+
+    // leaf pair kernel, source offset o = c_source - c_sink:
+    //   phi += K0 m, g += K1 m with K0 = -G/(h|o|), K1 = G o / (h^2 |o|^3)
+    const double h = P->h, G = P->G;
+    P->Ktab.assign((size_t)OFF_N * 4, 0.0);
+    for (int z = -OFF_R; z <= OFF_R; ++z)
+        for (int y = -OFF_R; y <= OFF_R; ++y)
+            for (int x = -OFF_R; x <= OFF_R; ++x) {
+                if (!x && !y && !z) continue;
+                const double d = std::sqrt((double)(x * x + y * y + z * z));
+                double *K = &P->Ktab[(size_t)off_index(x, y, z) * 4];
+                K[0] = -G / (h * d);
+                const double c = G / (h * h * d * d * d);
+                K[1] = c * x; K[2] = c * y; K[3] = c * z;
+            }
+
+    // derivative tensors per level l < L at R = z_sink - z_source = -o h_l
+    const int nlev = std::max(L, 1);
+    P->Dtab.assign((size_t)nlev * OFF_N * NC, 0.0);
+    for (int l = 0; l < L; ++l) {
+        const double hl = h * (double)(1 << (L - l));
+        for (int z = -OFF_R; z <= OFF_R; ++z)
+            for (int y = -OFF_R; y <= OFF_R; ++y)
+                for (int x = -OFF_R; x <= OFF_R; ++x) {
+                    if (!x && !y && !z) continue;
+                    derivative_tensor(G, -x * hl, -y * hl, -z * hl,
+                                      &P->Dtab[((size_t)l * OFF_N + off_index(x, y, z)) * NC]);
+                }
+    }
+
+    // M2L work items: deepest level first, the root's chunks last
+    P->items.clear();
+    for (int l = L - 1; l >= 1; --l) {
+        const int np = 4 << l;
+        const int bx = std::min(np, 64), by = std::min(np, 64 / bx), bz = 64 / (bx * by);
+        for (int z = 0; z < np; z += bz)
+            for (int y = 0; y < np; y += by)
+                for (int x = 0; x < np; x += bx) {
+                    M2LItem it{};
+                    it.level = l;
+                    it.q0[0] = x; it.q0[1] = y; it.q0[2] = z;
+                    it.pbeg = 0;
+                    it.pend = (int)P->plist_near.size();
+                    it.part = -1;
+                    P->items.push_back(it);
+                }
+    }
+    int nparts = 0;
+    if (L >= 1) {
+        const int ncube = (int)P->plist_cube.size();
+        for (int b = 0; b < ncube; b += ROOT_CHUNK) {
+            M2LItem it{};
+            it.level = 0;
+            it.pbeg = b;
+            it.pend = std::min(ncube, b + ROOT_CHUNK);
+            it.part = nparts++;
+            P->items.push_back(it);
+        }
+    }
+    P->dp.n_root_parts = nparts;
+}
+
+// ordered pairs and algorithmic work of the plan
+void fill_info(ot_fmm_plan P)
+{
+    ot_fmm_info &I = P->info;
+    std::memset(&I, 0, sizeof I);
+    const int L = P->L;
+    const int r2i = P->dp.r2i;
+    I.depth = L;
+    I.order = P->order;
+    I.theta = P->theta;
+    I.n_nodes = P->n_nodes;
+    I.n_leaf_nodes = P->n_leaf_nodes;
+    I.n_leaf_cells = P->n_leaf_nodes * 512;
+
+    auto parity_sum = [&](int n, bool far) {
+        // sum over sink parities b, near parent offsets P and source children b'
+        int64_t tot = 0;
+        for (int b = 0; b < 8; ++b)
+            for (const char4 &Pc : P->plist_near)
+                for (int bp = 0; bp < 8; ++bp) {
+                    const int o[3] = {2 * Pc.x + (bp & 1) - (b & 1), 2 * Pc.y + ((bp >> 1) & 1) - ((b >> 1) & 1),
+                                      2 * Pc.z + (bp >> 2) - (b >> 2)};
+                    const int o2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+                    if (o2 == 0 || (far && o2 <= r2i)) continue;
+                    tot += axis_count(n, b & 1, o[0]) * axis_count(n, (b >> 1) & 1, o[1]) *
+                           axis_count(n, b >> 2, o[2]);
+                }
+        return tot;
+    };
+    auto root_far = [&]() {
+        int64_t tot = 0;
+        for (int a = 0; a < 512; ++a)
+            for (int c = 0; c < 512; ++c) {
+                const int dx = (c & 7) - (a & 7), dy = ((c >> 3) & 7) - ((a >> 3) & 7), dz = (c >> 6) - (a >> 6);
+                if (dx * dx + dy * dy + dz * dz > r2i) ++tot;
+            }
+        return tot;
+    };
+
+    const int64_t N = I.n_leaf_cells;
+    I.p2p_pairs = (L == 0) ? (int64_t)512 * 511 : parity_sum(8 << L, false);
+    int64_t m2l = 0;
+    for (int l = 0; l < L; ++l) {
+        I.m2l_pairs_level[l] = (l == 0) ? root_far() : parity_sum(8 << l, true);
+        m2l += I.m2l_pairs_level[l];
+    }
+    I.m2l_pairs = m2l;
+
+    // algorithmic FLOP: 8 per P2P pair, 168 per M2L pair; M2M/L2L 84 FMA per
+    // cell of levels 1..L-1; leaves: 20 FMA into the first moments, 50 FMA
+    // of L2P (potential + gradient); adjoint leaves 50 (monopole + dipole)
+    // and 20 (potential).
+    int64_t internal_below_root = 0;
+    for (int l = 1; l < L; ++l) internal_below_root += (int64_t)(8 << l) * (8 << l) * (8 << l);
+    const double tree = 2.0 * 84.0 * 2.0 * (double)internal_below_root;   // M2M + L2L
+    const double lf = (L >= 1) ? 1.0 : 0.0;
+    I.flops_forward = 8.0 * (double)I.p2p_pairs + 168.0 * (double)m2l + tree + lf * 2.0 * (20.0 + 50.0) * (double)N;
+    I.flops_adjoint = 8.0 * (double)I.p2p_pairs + 168.0 * (double)m2l + tree + lf * 2.0 * (50.0 + 20.0) * (double)N;
+    // algorithmic bytes: leaf inputs and outputs once, plus every internal
+    // cell's moments and locals written once and read once
+    int64_t internal = 0;
+    for (int l = 0; l < L; ++l) internal += (int64_t)(8 << l) * (8 << l) * (8 << l);
+    const double tree_bytes = 4.0 * NC * 8.0 * (double)internal;
+    I.bytes_forward = 8.0 * N + 32.0 * N + tree_bytes;
+    I.bytes_adjoint = 32.0 * N + 8.0 * N + tree_bytes;
+}
+
+template <typename T>
+int dev_alloc(ot_fmm_plan P, T **ptr, size_t count, bool zero)
+{
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(OT_FMM_OUT_OF_MEMORY, std::string("hipMalloc of ") + std::to_string(bytes) +
+                                              " bytes failed: " + hipGetErrorString(e));
+    }
+    P->allocations.push_back(p);
+    P->info.device_bytes += bytes;
+    if (zero) {
+        e = hipMemset(p, 0, bytes);
+        if (e != hipSuccess) return hip_fail(e, "hipMemset");
+    }
+    *ptr = static_cast<T *>(p);
+    return OT_FMM_OK;
+}
+
+template <typename T>
+int dev_upload(ot_fmm_plan P, const T **dst, const std::vector<T> &src)
+{
+    T *p = nullptr;
+    int rc = dev_alloc(P, &p, src.size(), false);
+    if (rc) return rc;
+    if (!src.empty()) {
+        hipError_t e = hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    *dst = p;
+    return OT_FMM_OK;
+}
+
+void free_device(ot_fmm_plan P)
+{
+    for (void *p : P->allocations) (void)hipFree(p);
+    P->allocations.clear();
+    for (hipEvent_t ev : P->timing.pool) (void)hipEventDestroy(ev);
+    P->timing.pool.clear();
+}
+
+int setup_device(ot_fmm_plan P)
+{
+    hipError_t e = hipGetDevice(&P->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    DevPlan &d = P->dp;
+    const int L = P->L;
+    d.L = L;
+    d.hleaf = P->h;
+    d.G = P->G;
+    d.h3 = P->h * P->h * P->h;
+    d.sL = 1 << L;
+    d.npL = 4 << L;
+    d.hpL = (L == 0) ? 3 : 2;
+    d.ppL = d.npL + 2 * d.hpL;
+    d.n_leaf_cells = P->n_leaf_nodes * 512;
+    int rc;
+    if ((rc = dev_upload(P, &d.leaf_slot, P->leaf_slot))) return rc;
+    if ((rc = dev_upload(P, &d.Ktab, P->Ktab))) return rc;
+    if ((rc = dev_upload(P, &d.Dtab, P->Dtab))) return rc;
+    if ((rc = dev_upload(P, &d.plist_near, P->plist_near))) return rc;
+    if ((rc = dev_upload(P, &d.plist_cube, P->plist_cube))) return rc;
+    if ((rc = dev_upload(P, &d.items, P->items))) return rc;
+    d.n_plist_near = (int)P->plist_near.size();
+    d.n_plist_cube = (int)P->plist_cube.size();
+    d.plist_leaf = (L == 0) ? d.plist_cube : d.plist_near;
+    d.n_plist_leaf = (L == 0) ? d.n_plist_cube : d.n_plist_near;
+    d.n_items = (int)P->items.size();
+    if ((rc = dev_alloc(P, &d.root_part, (size_t)std::max(d.n_root_parts, 1) * NC * 8 * 64, true))) return rc;
+    const size_t ppL3 = (size_t)d.ppL * d.ppL * d.ppL;
+    if ((rc = dev_alloc(P, &d.src, 4 * 8 * ppL3, true))) return rc;
+    for (int l = 0; l < L; ++l) {
+        DevLevel &v = d.lev[l];
+        v.np = 4 << l;
+        v.hp = (l == 0) ? 3 : 2;
+        v.pp = v.np + 2 * v.hp;
+        v.h = P->h * (double)(1 << (L - l));
+        const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;
+        if ((rc = dev_alloc(P, &v.M, (size_t)NC * 8 * pp3, true))) return rc;
+        if ((rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize after plan setup");
+    P->has_device = true;
+    return OT_FMM_OK;
+}
+
+bool misaligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) != 0; }
+
+// --------------------------------------------------------------------------
+// timing of kernel phases with events on the call's stream
+// --------------------------------------------------------------------------
+struct Phase {
+    ot_fmm_plan P;
+    hipStream_t s;
+    int phase;
+    int launches;
+    hipEvent_t a = nullptr, b = nullptr;
+    Phase(ot_fmm_plan P_, hipStream_t s_, int phase_, int launches_) : P(P_), s(s_), phase(phase_), launches(launches_)
+    {
+        TimingState &T = P->timing;
+        if (!T.active || T.calls >= T.max_calls || T.next + 2 > T.pool.size()) return;
+        a = T.pool[T.next++];
+        b = T.pool[T.next++];
+        (void)hipEventRecord(a, s);
+    }
+    void end()
+    {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        P->timing.recs.push_back(TimingState::Rec{phase, launches, a, b});
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    bool switched = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) switched = (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard()
+    {
+        if (switched) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *ot_fmm_status_string(int s)
+{
+    switch (s) {
+    case OT_FMM_OK: return "OT_FMM_OK";
+    case OT_FMM_INVALID_ARGUMENT: return "OT_FMM_INVALID_ARGUMENT";
+    case OT_FMM_INVALID_LAYOUT: return "OT_FMM_INVALID_LAYOUT";
+    case OT_FMM_UNSUPPORTED_ORDER: return "OT_FMM_UNSUPPORTED_ORDER";
+    case OT_FMM_UNSUPPORTED_THETA: return "OT_FMM_UNSUPPORTED_THETA";
+    case OT_FMM_UNSUPPORTED_LAYOUT: return "OT_FMM_UNSUPPORTED_LAYOUT";
+    case OT_FMM_OUT_OF_MEMORY: return "OT_FMM_OUT_OF_MEMORY";
+    case OT_FMM_DEVICE_ERROR: return "OT_FMM_DEVICE_ERROR";
+    case OT_FMM_NO_DEVICE_STATE: return "OT_FMM_NO_DEVICE_STATE";
+    default: return "OT_FMM_UNKNOWN_STATUS";
+    }
+}
+
+const char *ot_fmm_last_error(void) { return g_err.c_str(); }
+
+const char *ot_fmm_phase_name(int phase)
+{
+    static const char *names[OT_FMM_NUM_PHASES] = {"upward_leaf", "m2m", "m2l", "l2l",
+                                                   "leaf", "upward_leaf_adj", "leaf_adj", "total"};
+    return (phase >= 0 && phase < OT_FMM_NUM_PHASES) ? names[phase] : "unknown";
+}
+
+int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order, uint32_t flags,
+                       ot_fmm_plan *out)
+{
+    if (!out) return fail(OT_FMM_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (flags & ~OT_FMM_HOST_ONLY) return fail(OT_FMM_INVALID_ARGUMENT, "unknown flag bits");
+    if (!std::isfinite(theta) || theta <= 0.0) return fail(OT_FMM_INVALID_ARGUMENT, "theta must be finite and > 0");
+    if (!(theta > 1.0 / 3.0 && theta <= 1.0))
+        return fail(OT_FMM_UNSUPPORTED_THETA, "theta must lie in (1/3, 1] (near radius 1/theta in [1, 3) cells)");
+    if (order != 3) return fail(OT_FMM_UNSUPPORTED_ORDER, "only expansion order 3 is implemented");
+    ot_fmm_plan P = new (std::nothrow) ot_fmm_plan_s();
+    if (!P) return fail(OT_FMM_OUT_OF_MEMORY, "host allocation of the plan failed");
+    P->theta = theta;
+    P->order = order;
+    P->flags = flags;
+    const double rn = 1.0 / theta;
+    P->r2 = rn * rn;
+    int rc = validate_layout(layout, P);
+    if (rc) { delete P; return rc; }
+    try {
+        build_tables(P);
+        fill_info(P);
+    } catch (const std::bad_alloc &) {
+        delete P;
+        return fail(OT_FMM_OUT_OF_MEMORY, "host allocation of the tables failed");
+    }
+    if (!(flags & OT_FMM_HOST_ONLY)) {
+        rc = setup_device(P);
+        if (rc) {
+            free_device(P);
+            delete P;
+            return rc;
+        }
+    }
+    *out = P;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_plan_info(ot_fmm_plan P, ot_fmm_info *info)
+{
+    if (!P || !info) return fail(OT_FMM_INVALID_ARGUMENT, "plan or info is NULL");
+    *info = P->info;
+    return OT_FMM_OK;
+}
+
+void ot_fmm_destroy(ot_fmm_plan P)
+{
+    if (!P) return;
+    if (P->has_device) {
+        DeviceGuard g(P->device);
+        free_device(P);
+    }
+    delete P;
+}
+
+int ot_fmm_forward(ot_fmm_plan P, const double *rho, double *phi, double *g, void *hip_stream)
+{
+    if (!P) return fail(OT_FMM_INVALID_ARGUMENT, "plan is NULL");
+    if (!P->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "plan was created with OT_FMM_HOST_ONLY");
+    if (!rho || !phi || !g) return fail(OT_FMM_INVALID_ARGUMENT, "NULL device pointer");
+    if (misaligned(rho) || misaligned(phi) || misaligned(g))
+        return fail(OT_FMM_INVALID_ARGUMENT, "device pointers must be 8-byte aligned");
+    DeviceGuard guard(P->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const DevPlan &d = P->dp;
+    hipError_t e;
+    Phase total(P, s, OT_FMM_PHASE_TOTAL, 0);
+    {
+        Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF, 1);
+        if ((e = launch_upward_leaf(d, rho, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf");
+        ph.end();
+    }
+    if (P->L >= 2) {
+        Phase ph(P, s, OT_FMM_PHASE_M2M, P->L - 1);
+        for (int l = P->L - 2; l >= 0; --l)
+            if ((e = launch_m2m(d, l, s)) != hipSuccess) return hip_fail(e, "launch m2m");
+        ph.end();
+    }
+    if (P->L >= 1) {
+        {
+            Phase ph(P, s, OT_FMM_PHASE_M2L, 1);
+            if ((e = launch_m2l(d, s)) != hipSuccess) return hip_fail(e, "launch m2l");
+            ph.end();
+        }
+        Phase ph(P, s, OT_FMM_PHASE_L2L, P->L);
+        if ((e = launch_root_reduce(d, s)) != hipSuccess) return hip_fail(e, "launch root_reduce");
+        for (int l = 1; l < P->L; ++l)
+            if ((e = launch_l2l(d, l, s)) != hipSuccess) return hip_fail(e, "launch l2l");
+        ph.end();
+    }
+    {
+        Phase ph(P, s, OT_FMM_PHASE_LEAF, 1);
+        if ((e = launch_leaf(d, phi, g, s)) != hipSuccess) return hip_fail(e, "launch leaf");
+        ph.end();
+    }
+    total.end();
+    if (P->timing.active && P->timing.calls < P->timing.max_calls) P->timing.calls++;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_adjoint(ot_fmm_plan P, const double *dphi, const double *dg, double *drho, void *hip_stream)
+{
+    if (!P) return fail(OT_FMM_INVALID_ARGUMENT, "plan is NULL");
+    if (!P->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "plan was created with OT_FMM_HOST_ONLY");
+    if (!dphi || !dg || !drho) return fail(OT_FMM_INVALID_ARGUMENT, "NULL device pointer");
+    if (misaligned(dphi) || misaligned(dg) || misaligned(drho))
+        return fail(OT_FMM_INVALID_ARGUMENT, "device pointers must be 8-byte aligned");
+    DeviceGuard guard(P->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const DevPlan &d = P->dp;
+    hipError_t e;
+    Phase total(P, s, OT_FMM_PHASE_TOTAL, 0);
+    {
+        Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF_ADJ, 1);
+        if ((e = launch_upward_leaf_adj(d, dphi, dg, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf_adj");
+        ph.end();
+    }
+    if (P->L >= 2) {
+        Phase ph(P, s, OT_FMM_PHASE_M2M, P->L - 1);
+        for (int l = P->L - 2; l >= 0; --l)
+            if ((e = launch_m2m(d, l, s)) != hipSuccess) return hip_fail(e, "launch m2m");
+        ph.end();
+    }
+    if (P->L >= 1) {
+        {
+            Phase ph(P, s, OT_FMM_PHASE_M2L, 1);
+            if ((e = launch_m2l(d, s)) != hipSuccess) return hip_fail(e, "launch m2l");
+            ph.end();
+        }
+        Phase ph(P, s, OT_FMM_PHASE_L2L, P->L);
+        if ((e = launch_root_reduce(d, s)) != hipSuccess) return hip_fail(e, "launch root_reduce");
+        for (int l = 1; l < P->L; ++l)
+            if ((e = launch_l2l(d, l, s)) != hipSuccess) return hip_fail(e, "launch l2l");
+        ph.end();
+    }
+    {
+        Phase ph(P, s, OT_FMM_PHASE_LEAF_ADJ, 1);
+        if ((e = launch_leaf_adj(d, drho, s)) != hipSuccess) return hip_fail(e, "launch leaf_adj");
+        ph.end();
+    }
+    total.end();
+    if (P->timing.active && P->timing.calls < P->timing.max_calls) P->timing.calls++;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_timing_begin(ot_fmm_plan P, int max_calls)
+{
+    if (!P || max_calls < 1) return fail(OT_FMM_INVALID_ARGUMENT, "plan is NULL or max_calls < 1");
+    if (!P->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "plan was created with OT_FMM_HOST_ONLY");
+    DeviceGuard guard(P->device);
+    TimingState &T = P->timing;
+    for (hipEvent_t ev : T.pool) (void)hipEventDestroy(ev);
+    T = TimingState{};
+    const size_t need = (size_t)max_calls * 2 * OT_FMM_NUM_PHASES;
+    T.pool.reserve(need);
+    for (size_t i = 0; i < need; ++i) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            for (hipEvent_t x : T.pool) (void)hipEventDestroy(x);
+            T.pool.clear();
+            return hip_fail(e, "hipEventCreate");
+        }
+        T.pool.push_back(ev);
+    }
+    T.active = true;
+    T.max_calls = max_calls;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_timing_end(ot_fmm_plan P, ot_fmm_timing *out)
+{
+    if (!P || !out) return fail(OT_FMM_INVALID_ARGUMENT, "plan or out is NULL");
+    if (!P->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "plan was created with OT_FMM_HOST_ONLY");
+    DeviceGuard guard(P->device);
+    TimingState &T = P->timing;
+    std::memset(out, 0, sizeof *out);
+    out->calls = T.calls;
+    int rc = OT_FMM_OK;
+    for (const auto &r : T.recs) {
+        hipError_t e = hipEventSynchronize(r.b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) { rc = hip_fail(e, "timing events"); break; }
+        out->ms[r.phase] += ms;
+        out->events[r.phase] += 1;
+        out->launches[r.phase] += r.launches;
+    }
+    for (hipEvent_t ev : T.pool) (void)hipEventDestroy(ev);
+    T = TimingState{};
+    return rc;
+}
+
+}  // extern "C"

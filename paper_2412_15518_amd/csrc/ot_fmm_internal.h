@@ -1,0 +1,127 @@
+// ot_fmm_internal.h -- plan state and kernel launchers of the HIP FMM library.
+//
+// Storage (all FP64, device-resident, allocated once per plan):
+//   A cell c of level l is addressed through its parent q = c >> 1 and its
+//   child index b = (c_x & 1) + 2 (c_y & 1) + 4 (c_z & 1).  Every level below
+//   the leaves keeps
+//     M[l] : scaled moments   [NC][8][pp^3]  over the parent grid padded by a
+//            zero halo of hp parents per side (pp = np + 2 hp, np = n_l / 2),
+//     C[l] : local coefficients [NC][8][np^3],
+//   so the 64 lanes of a wave that handle 64 neighbouring parents read
+//   consecutive addresses, and the stencil never needs a bounds check.
+//   The leaf sources (masses, or the adjoint's cotangents) are staged in the
+//   same padded form: src[plane][8][ppL^3].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ot_fmm.h"
+
+namespace otfmm {
+
+constexpr int NC = 20;                          // components of orders 0..3
+constexpr int SUB = 8;                          // cells per sub-grid axis
+constexpr int OFF_R = 7;                        // offset tables span [-7, 7]^3
+constexpr int OFF_W = 2 * OFF_R + 1;
+constexpr int OFF_N = OFF_W * OFF_W * OFF_W;    // 3375
+constexpr int MAX_LEVELS = 8;                   // leaf level L <= 7
+constexpr int ROOT_CHUNK = 16;                  // parent offsets per root M2L work item
+constexpr int WG = 256;                         // threads per workgroup (4 waves)
+
+__host__ __device__ inline int off_index(int ox, int oy, int oz)
+{
+    return ((oz + OFF_R) * OFF_W + (oy + OFF_R)) * OFF_W + (ox + OFF_R);
+}
+
+struct DevLevel {
+    int np;          // parents per axis (n_l / 2)
+    int hp;          // halo of the moment array, in parents
+    int pp;          // np + 2 hp
+    int pad_;
+    double h;        // cell width of this level
+    double *M;       // [NC][8][pp^3]
+    double *C;       // [NC][8][np^3]
+};
+
+// One M2L work item = one workgroup: 64 sink parents of one level (a block
+// of bx*by*bz parents starting at q0) and a range of parent offsets.
+struct M2LItem {
+    int level;
+    int q0[3];
+    int pbeg, pend;  // range in the level's parent-offset list
+    int part;        // root partial-sum slot, -1 for levels >= 1
+    int pad_;
+};
+
+struct DevPlan {
+    int L;               // leaf level
+    int r2i;             // largest integer k with k <= (1/theta)^2: far iff |o|^2 > r2i
+    double hleaf, G, h3;
+    int npL, hpL, ppL;   // leaf parents per axis, their halo, padded width
+    int sL;              // leaf sub-grids per axis (2^L)
+    int64_t n_leaf_cells;
+    const int32_t *leaf_slot;   // [sL^3] leaf index in layout order
+    double *src;                // [4][8][ppL^3]
+    const double *Ktab;         // [OFF_N][4]: K0, K1x, K1y, K1z of a leaf pair
+    const double *Dtab;         // [L][OFF_N][NC]: derivative tensor of -G/r per level
+    const char4 *plist_leaf; int n_plist_leaf;   // parent offsets of the leaf P2P
+    const char4 *plist_near; int n_plist_near;   // |P| <= 1/theta (levels >= 1)
+    const char4 *plist_cube; int n_plist_cube;   // [-3,3]^3 (root level)
+    const M2LItem *items; int n_items;
+    double *root_part; int n_root_parts;         // [parts][NC][8][64]
+    DevLevel lev[MAX_LEVELS];
+};
+
+struct TimingState {
+    bool active = false;
+    int max_calls = 0;
+    int calls = 0;
+    std::vector<hipEvent_t> pool;      // pre-created events
+    size_t next = 0;
+    struct Rec { int phase; int launches; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+};
+
+}  // namespace otfmm
+
+struct ot_fmm_plan_s {
+    int L = 0;
+    int order = 3;
+    double theta = 0.4;
+    double r2 = 6.25;
+    uint32_t flags = 0;
+    double h = 1.0, G = 1.0;
+    int64_t n_nodes = 0, n_leaf_nodes = 0;
+    int device = -1;
+    bool has_device = false;
+
+    // host tables
+    std::vector<int32_t> leaf_slot;
+    std::vector<char4> plist_near, plist_cube;
+    std::vector<otfmm::M2LItem> items;
+    std::vector<double> Ktab, Dtab;
+    ot_fmm_info info{};
+
+    // device state
+    otfmm::DevPlan dp{};
+    std::vector<void *> allocations;
+    otfmm::TimingState timing;
+};
+
+namespace otfmm {
+
+// kernel launchers (ot_fmm_kernels.hip); each returns hipGetLastError()
+hipError_t launch_upward_leaf(const DevPlan &p, const double *rho, hipStream_t s);
+hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const double *u, hipStream_t s);
+hipError_t launch_m2m(const DevPlan &p, int level, hipStream_t s);
+hipError_t launch_m2l(const DevPlan &p, hipStream_t s);
+hipError_t launch_root_reduce(const DevPlan &p, hipStream_t s);
+hipError_t launch_l2l(const DevPlan &p, int level, hipStream_t s);
+hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s);
+hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s);
+
+}  // namespace otfmm

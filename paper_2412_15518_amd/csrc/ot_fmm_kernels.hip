@@ -1,0 +1,584 @@
+// ot_fmm_kernels.hip -- gfx950 kernels of the octree FMM gravity solve.
+//
+// Expansion algebra (order p = 3, 20 components each, expansions about
+// geometric cell centres; the paper, Sec. 4.3, names an FMM on 8^3 sub-grids
+// and Sec. 5.5 its same-level stencil, without formulas):
+//   scaled moments    Mt_A^a = sum_i m_i (z_A - x_i)^a / a!
+//   local coefficients C_A^a = d^a phi at z_A  (Taylor coefficients times a!)
+//   e_a(x) = x^a / a!  (component order below)
+//   M2M   Mt_P^a += sum_{b <= a} e_{a-b}(z_P - z_c) Mt_c^b
+//   M2L   C_A^a  += sum_{|a|+|b| <= 3} D^{a+b}(z_A - z_B) Mt_B^b,
+//         D = derivative tensor of K(r) = -G/|r|
+//   L2L   C_c^a  += sum_{|a|+|g| <= 3} e_g(z_c - z_P) C_P^{a+g}
+//   L2P   phi = C^0, g = -C^{e_k} at the leaf centre
+//   P2P   phi_i += K0(o) m_{i+o}, g_i += K1(o) m_{i+o} for every leaf pair whose
+//         parents are near (the far children of near parents included: with
+//         point-mass leaves both evaluations are exact and coincide).
+// The adjoint runs the same pipeline on dual sources: its transpose equals the
+// forward chain applied to a leaf monopole w and scaled dipole u (see the
+// derivation in the design notes); only the leaf stages differ.
+//
+// Work mapping: a lane owns one parent cell q of the level and the children
+// 2q + b of it, so every stencil offset o = 2P + b' - b is uniform across a
+// wave (P from the parent-offset list, b' the source child, b the sink child):
+// the tables K(o) and D(o) arrive through scalar loads, and the moments of
+// the 64 neighbouring parents are contiguous in memory.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "ot_fmm_internal.h"
+
+namespace otfmm {
+
+// ------------------------------------------------------------------------
+// component order: by total order, then x-power descending, then y-power
+// ------------------------------------------------------------------------
+struct MIdx { int t, u, v; };
+constexpr MIdx kMI[NC] = {
+    {0, 0, 0},
+    {1, 0, 0}, {0, 1, 0}, {0, 0, 1},
+    {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
+    {3, 0, 0}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 1, 1}, {1, 0, 2},
+    {0, 3, 0}, {0, 2, 1}, {0, 1, 2}, {0, 0, 3}};
+
+constexpr int comp_of(int t, int u, int v)
+{
+    for (int k = 0; k < NC; ++k)
+        if (kMI[k].t == t && kMI[k].u == u && kMI[k].v == v) return k;
+    return -1;
+}
+constexpr int order_of(int k) { return kMI[k].t + kMI[k].u + kMI[k].v; }
+
+struct Term { int i, j, k; };
+template <int N>
+struct Terms { Term t[N]; int n; };
+
+// (a, b, a+b) with |a| + |b| <= 3: M2L  C[a] += D[a+b] M[b];
+//                                   L2L  C[a] += e[b] Cp[a+b]
+constexpr Terms<84> make_sum_terms()
+{
+    Terms<84> T{};
+    T.n = 0;
+    for (int a = 0; a < NC; ++a)
+        for (int b = 0; b < NC; ++b)
+            if (order_of(a) + order_of(b) <= 3)
+                T.t[T.n++] = {a, b, comp_of(kMI[a].t + kMI[b].t, kMI[a].u + kMI[b].u, kMI[a].v + kMI[b].v)};
+    return T;
+}
+
+// (a, b, a-b) with b <= a componentwise: M2M  Mp[a] += e[a-b] Mc[b]
+constexpr Terms<84> make_sub_terms()
+{
+    Terms<84> T{};
+    T.n = 0;
+    for (int a = 0; a < NC; ++a)
+        for (int b = 0; b < NC; ++b)
+            if (kMI[b].t <= kMI[a].t && kMI[b].u <= kMI[a].u && kMI[b].v <= kMI[a].v)
+                T.t[T.n++] = {a, b, comp_of(kMI[a].t - kMI[b].t, kMI[a].u - kMI[b].u, kMI[a].v - kMI[b].v)};
+    return T;
+}
+
+// (a, k, a - e_k) with a_k >= 1: dipole source  Mp[a] += u_k e[a - e_k]
+constexpr Terms<30> make_dipole_terms()
+{
+    Terms<30> T{};
+    T.n = 0;
+    for (int a = 0; a < NC; ++a)
+        for (int k = 0; k < 3; ++k) {
+            int t = kMI[a].t - (k == 0), u = kMI[a].u - (k == 1), v = kMI[a].v - (k == 2);
+            if (t >= 0 && u >= 0 && v >= 0) T.t[T.n++] = {a, k, comp_of(t, u, v)};
+        }
+    return T;
+}
+
+// (k, g, g + e_k) with |g| <= 2: gradient of the local expansion at the leaf
+//   dphi/dx_k = sum_g e[g] C[g + e_k]
+constexpr Terms<30> make_grad_terms()
+{
+    Terms<30> T{};
+    T.n = 0;
+    for (int k = 0; k < 3; ++k)
+        for (int g = 0; g < NC; ++g)
+            if (order_of(g) <= 2)
+                T.t[T.n++] = {k, g, comp_of(kMI[g].t + (k == 0), kMI[g].u + (k == 1), kMI[g].v + (k == 2))};
+    return T;
+}
+
+static_assert(make_sum_terms().n == 84, "84 terms of total order <= 3");
+static_assert(make_sub_terms().n == 84, "84 shift terms");
+static_assert(make_dipole_terms().n == 30, "30 dipole terms");
+static_assert(make_grad_terms().n == 30, "30 gradient terms");
+
+// C[a] += D[a+b] M[b] over all 84 terms
+template <int... I>
+__device__ __forceinline__ void m2l_terms(double *C, const double *D, const double *M,
+                                          std::integer_sequence<int, I...>)
+{
+    constexpr Terms<84> T = make_sum_terms();
+    ((C[T.t[I].i] = fma(D[T.t[I].k], M[T.t[I].j], C[T.t[I].i])), ...);
+}
+__device__ __forceinline__ void m2l_apply(double *C, const double *D, const double *M)
+{
+    m2l_terms(C, D, M, std::make_integer_sequence<int, 84>{});
+}
+
+// Cc[a] += e[g] Cp[a+g]
+template <int... I>
+__device__ __forceinline__ void l2l_terms(double *Cc, const double *e, const double *Cp,
+                                          std::integer_sequence<int, I...>)
+{
+    constexpr Terms<84> T = make_sum_terms();
+    ((Cc[T.t[I].i] = fma(e[T.t[I].j], Cp[T.t[I].k], Cc[T.t[I].i])), ...);
+}
+__device__ __forceinline__ void l2l_apply(double *Cc, const double *e, const double *Cp)
+{
+    l2l_terms(Cc, e, Cp, std::make_integer_sequence<int, 84>{});
+}
+
+// Mp[a] += e[a-b] Mc[b]
+template <int... I>
+__device__ __forceinline__ void m2m_terms(double *Mp, const double *e, const double *Mc,
+                                          std::integer_sequence<int, I...>)
+{
+    constexpr Terms<84> T = make_sub_terms();
+    ((Mp[T.t[I].i] = fma(e[T.t[I].k], Mc[T.t[I].j], Mp[T.t[I].i])), ...);
+}
+__device__ __forceinline__ void m2m_apply(double *Mp, const double *e, const double *Mc)
+{
+    m2m_terms(Mp, e, Mc, std::make_integer_sequence<int, 84>{});
+}
+
+// Mp[a] += u[k] e[a - e_k]
+template <int... I>
+__device__ __forceinline__ void dipole_terms(double *Mp, const double *e, const double *u,
+                                             std::integer_sequence<int, I...>)
+{
+    constexpr Terms<30> T = make_dipole_terms();
+    ((Mp[T.t[I].i] = fma(u[T.t[I].j], e[T.t[I].k], Mp[T.t[I].i])), ...);
+}
+__device__ __forceinline__ void dipole_apply(double *Mp, const double *e, const double *u)
+{
+    dipole_terms(Mp, e, u, std::make_integer_sequence<int, 30>{});
+}
+
+// grad[k] += e[g] C[g + e_k]
+template <int... I>
+__device__ __forceinline__ void grad_terms(double *grad, const double *e, const double *C,
+                                           std::integer_sequence<int, I...>)
+{
+    constexpr Terms<30> T = make_grad_terms();
+    ((grad[T.t[I].i] = fma(e[T.t[I].j], C[T.t[I].k], grad[T.t[I].i])), ...);
+}
+__device__ __forceinline__ void grad_apply(double *grad, const double *e, const double *C)
+{
+    grad_terms(grad, e, C, std::make_integer_sequence<int, 30>{});
+}
+
+// e_a(x) = x^a / a!
+__device__ __forceinline__ void taylor(double x, double y, double z, double *e)
+{
+    const double x2 = 0.5 * x * x, y2 = 0.5 * y * y, z2 = 0.5 * z * z;
+    e[0] = 1.0;
+    e[1] = x; e[2] = y; e[3] = z;
+    e[4] = x2; e[5] = x * y; e[6] = x * z; e[7] = y2; e[8] = y * z; e[9] = z2;
+    e[10] = x2 * x * (1.0 / 3.0); e[11] = x2 * y; e[12] = x2 * z; e[13] = x * y2; e[14] = x * y * z;
+    e[15] = x * z2; e[16] = y2 * y * (1.0 / 3.0); e[17] = y2 * z; e[18] = y * z2; e[19] = z2 * z * (1.0 / 3.0);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// 64 lanes of a wave cover a block of bx*by*bz parents of an np^3 grid
+struct Block { int bx, by, bz; };
+__host__ __device__ inline Block block_shape(int np)
+{
+    Block b;
+    b.bx = np < 64 ? np : 64;
+    b.by = np < 64 / b.bx ? np : 64 / b.bx;
+    b.bz = 64 / (b.bx * b.by);
+    return b;
+}
+
+// ------------------------------------------------------------------------
+// P2M + M2M into level L-1 (forward): lane = one leaf parent Q
+// ------------------------------------------------------------------------
+template <bool ADJ>
+__global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const double *__restrict__ a0,
+                                                    const double *__restrict__ a1)
+{
+    const int npL = p.npL;
+    const int64_t nQ = (int64_t)npL * npL * npL;
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= nQ) return;
+    const int Qx = (int)(t % npL), Qy = (int)((t / npL) % npL), Qz = (int)(t / ((int64_t)npL * npL));
+    const int64_t ppL3 = (int64_t)p.ppL * p.ppL * p.ppL;
+    const int64_t padQ = ((int64_t)(Qz + p.hpL) * p.ppL + (Qy + p.hpL)) * p.ppL + (Qx + p.hpL);
+    const int sx = Qx >> 2, sy = Qy >> 2, sz = Qz >> 2;
+    const int64_t base = (int64_t)p.leaf_slot[((int64_t)sz * p.sL + sy) * p.sL + sx] * 512;
+    const int lx0 = (2 * Qx) & 7, ly0 = (2 * Qy) & 7, lz0 = (2 * Qz) & 7;
+    const int64_t N = p.n_leaf_cells;
+    const double hh = 0.5 * p.hleaf;
+    double Mq[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Mq[k] = 0.0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+        const int64_t idx = base + ((lz0 + bz) * 8 + (ly0 + by)) * 8 + (lx0 + bx);
+        double e[NC];
+        taylor(bx ? -hh : hh, by ? -hh : hh, bz ? -hh : hh, e);    // e(z_Q - z_child)
+        if (!ADJ) {
+            const double m = a0[idx] * p.h3;
+            p.src[b * ppL3 + padQ] = m;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], m, Mq[k]);
+        } else {
+            const double w = a0[idx];
+            double u[3] = {a1[idx], a1[N + idx], a1[2 * N + idx]};
+            p.src[(0 * 8 + b) * ppL3 + padQ] = w;
+            p.src[(1 * 8 + b) * ppL3 + padQ] = u[0];
+            p.src[(2 * 8 + b) * ppL3 + padQ] = u[1];
+            p.src[(3 * 8 + b) * ppL3 + padQ] = u[2];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], w, Mq[k]);
+            dipole_apply(Mq, e, u);
+        }
+    }
+    if (p.L >= 1) {
+        const DevLevel &D = p.lev[p.L - 1];
+        const int bself = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
+        const int64_t pp3 = (int64_t)D.pp * D.pp * D.pp;
+        const int64_t padq = ((int64_t)((Qz >> 1) + D.hp) * D.pp + ((Qy >> 1) + D.hp)) * D.pp + ((Qx >> 1) + D.hp);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) D.M[(k * 8 + bself) * pp3 + padq] = Mq[k];
+    }
+}
+
+// ------------------------------------------------------------------------
+// M2M into level l from level l+1: lane = one cell c of level l
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_m2m(const DevPlan p, int l)
+{
+    const DevLevel &D = p.lev[l];
+    const DevLevel &Dc = p.lev[l + 1];
+    const int n = 2 * D.np;
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * n * n) return;
+    const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
+    const int64_t ppc3 = (int64_t)Dc.pp * Dc.pp * Dc.pp;
+    const int64_t padc = ((int64_t)(cz + Dc.hp) * Dc.pp + (cy + Dc.hp)) * Dc.pp + (cx + Dc.hp);
+    const double hh = 0.5 * Dc.h;
+    double Mp[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Mp[k] = 0.0;
+#pragma unroll 1
+    for (int b = 0; b < 8; ++b) {
+        double Mc[NC], e[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Mc[k] = Dc.M[(k * 8 + b) * ppc3 + padc];
+        taylor((b & 1) ? -hh : hh, ((b >> 1) & 1) ? -hh : hh, (b >> 2) ? -hh : hh, e);
+        m2m_apply(Mp, e, Mc);
+    }
+    const int bself = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+    const int64_t pp3 = (int64_t)D.pp * D.pp * D.pp;
+    const int64_t padq = ((int64_t)((cz >> 1) + D.hp) * D.pp + ((cy >> 1) + D.hp)) * D.pp + ((cx >> 1) + D.hp);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) D.M[(k * 8 + bself) * pp3 + padq] = Mp[k];
+}
+
+// ------------------------------------------------------------------------
+// M2L, every level below the leaves in one launch.  Workgroup = one work
+// item (64 sink parents x one range of parent offsets); wave w handles the
+// sink children b = 2w and 2w+1 of its lane's parent.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_m2l(const DevPlan p)
+{
+    const M2LItem it = p.items[blockIdx.x];
+    const int lev = it.level;
+    const DevLevel &D = p.lev[lev];
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform(threadIdx.x >> 6);
+    const Block bs = block_shape(D.np);
+    const int qx = it.q0[0] + lane % bs.bx;
+    const int qy = it.q0[1] + (lane / bs.bx) % bs.by;
+    const int qz = it.q0[2] + lane / (bs.bx * bs.by);
+    const int b0 = 2 * wave, b1 = 2 * wave + 1;
+    const int64_t pp = D.pp;
+    const int64_t pp3 = pp * pp * pp;
+    const double *__restrict__ Mb = D.M + ((qz + D.hp) * pp + (qy + D.hp)) * pp + (qx + D.hp);
+    const double *__restrict__ Dl = p.Dtab + (size_t)lev * OFF_N * NC;
+    const char4 *plist = lev == 0 ? p.plist_cube : p.plist_near;
+    const int r2i = p.r2i;
+
+    double C0[NC], C1[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) { C0[k] = 0.0; C1[k] = 0.0; }
+
+    for (int pi = it.pbeg; pi < it.pend; ++pi) {
+        const char4 P = plist[pi];
+        const int64_t poff = ((int64_t)P.z * pp + P.y) * pp + P.x;
+#pragma unroll 1
+        for (int bp = 0; bp < 8; ++bp) {
+            double Ms[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) Ms[k] = Mb[(k * 8 + bp) * pp3 + poff];
+            const int sx = 2 * P.x + (bp & 1), sy = 2 * P.y + ((bp >> 1) & 1), sz = 2 * P.z + (bp >> 2);
+            {
+                const int ox = sx - (b0 & 1), oy = sy - ((b0 >> 1) & 1), oz = sz - (b0 >> 2);
+                if (ox * ox + oy * oy + oz * oz > r2i) {
+                    const double *Dr = Dl + off_index(ox, oy, oz) * NC;
+                    double Dv[NC];
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) Dv[k] = Dr[k];
+                    m2l_apply(C0, Dv, Ms);
+                }
+            }
+            {
+                const int ox = sx - (b1 & 1), oy = sy - ((b1 >> 1) & 1), oz = sz - (b1 >> 2);
+                if (ox * ox + oy * oy + oz * oz > r2i) {
+                    const double *Dr = Dl + off_index(ox, oy, oz) * NC;
+                    double Dv[NC];
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) Dv[k] = Dr[k];
+                    m2l_apply(C1, Dv, Ms);
+                }
+            }
+        }
+    }
+
+    const int64_t np = D.np;
+    const int64_t q = (qz * np + qy) * np + qx;
+    if (it.part < 0) {
+        const int64_t np3 = np * np * np;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            D.C[(k * 8 + b0) * np3 + q] = C0[k];
+            D.C[(k * 8 + b1) * np3 + q] = C1[k];
+        }
+    } else {
+        double *R = p.root_part + (size_t)it.part * NC * 8 * 64;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            R[(k * 8 + b0) * 64 + q] = C0[k];
+            R[(k * 8 + b1) * 64 + q] = C1[k];
+        }
+    }
+}
+
+// root local coefficients = sum of the partial sums of its work items
+__global__ __launch_bounds__(WG) void k_root_reduce(const DevPlan p)
+{
+    const int t = blockIdx.x * WG + threadIdx.x;
+    if (t >= NC * 8 * 64) return;
+    double s = 0.0;
+    for (int part = 0; part < p.n_root_parts; ++part) s += p.root_part[(size_t)part * NC * 8 * 64 + t];
+    p.lev[0].C[t] = s;
+}
+
+// ------------------------------------------------------------------------
+// L2L into level l >= 1 from level l-1: lane = one cell c of level l
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_l2l(const DevPlan p, int l)
+{
+    const DevLevel &D = p.lev[l];
+    const DevLevel &Dp = p.lev[l - 1];
+    const int n = 2 * D.np;
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * n * n) return;
+    const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
+    // parent cell P = c >> 1 of level l-1, stored under its own parent P >> 1
+    const int Px = cx >> 1, Py = cy >> 1, Pz = cz >> 1;
+    const int bP = (Px & 1) + 2 * (Py & 1) + 4 * (Pz & 1);
+    const int64_t npp = Dp.np;
+    const int64_t qP = (((int64_t)(Pz >> 1)) * npp + (Py >> 1)) * npp + (Px >> 1);
+    const int64_t npp3 = npp * npp * npp;
+    double Cp[NC], e[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Cp[k] = Dp.C[(k * 8 + bP) * npp3 + qP];
+    const double hh = 0.5 * D.h;
+    taylor((cx & 1) ? hh : -hh, (cy & 1) ? hh : -hh, (cz & 1) ? hh : -hh, e);   // e(z_c - z_P)
+    const int bself = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+    const int64_t np = D.np;
+    const int64_t np3 = np * np * np;
+    const int64_t q = (((int64_t)(cz >> 1)) * np + (cy >> 1)) * np + (cx >> 1);
+    double Cc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Cc[k] = D.C[(k * 8 + bself) * np3 + q];
+    l2l_apply(Cc, e, Cp);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) D.C[(k * 8 + bself) * np3 + q] = Cc[k];
+}
+
+// ------------------------------------------------------------------------
+// Leaf pass: P2P over the leaf stencil + L2L/L2P from level L-1.
+// A wave owns 64 leaf parents Q (lane = Q) and all 8 children of each.
+// ------------------------------------------------------------------------
+template <bool ADJ>
+__global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, double *__restrict__ out0,
+                                             double *__restrict__ out1)
+{
+    const int npL = p.npL;
+    const Block bs = block_shape(npL);
+    const int nbx = npL / bs.bx, nby = npL / bs.by, nbz = npL / bs.bz;
+    const int blk = blockIdx.x * (WG / 64) + uniform(threadIdx.x >> 6);
+    if (blk >= nbx * nby * nbz) return;
+    const int lane = threadIdx.x & 63;
+    const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
+    const int Qy = ((blk / nbx) % nby) * bs.by + (lane / bs.bx) % bs.by;
+    const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
+    const int64_t pp = p.ppL;
+    const int64_t ppL3 = pp * pp * pp;
+    const double *__restrict__ S = p.src + ((Qz + p.hpL) * pp + (Qy + p.hpL)) * pp + (Qx + p.hpL);
+
+    // forward: phi, g_x, g_y, g_z per sink child; adjoint: one sum per sink child
+    constexpr int NA = ADJ ? 1 : 4;
+    double acc[8][NA];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int j = 0; j < NA; ++j) acc[b][j] = 0.0;
+
+    for (int pi = 0; pi < p.n_plist_leaf; ++pi) {
+        const char4 P = p.plist_leaf[pi];
+        const int64_t poff = ((int64_t)P.z * pp + P.y) * pp + P.x;
+#pragma unroll 1
+        for (int bp = 0; bp < 8; ++bp) {
+            const int sx = 2 * P.x + (bp & 1), sy = 2 * P.y + ((bp >> 1) & 1), sz = 2 * P.z + (bp >> 2);
+            double src[4];
+            if constexpr (!ADJ) {
+                src[0] = S[bp * ppL3 + poff];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) src[j] = S[(j * 8 + bp) * ppL3 + poff];
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int ox = sx - (b & 1), oy = sy - ((b >> 1) & 1), oz = sz - (b >> 2);
+                const double *K = p.Ktab + off_index(ox, oy, oz) * 4;
+                const double k0 = K[0], k1 = K[1], k2 = K[2], k3 = K[3];
+                if constexpr (!ADJ) {
+                    acc[b][0] = fma(k0, src[0], acc[b][0]);
+                    acc[b][1 % NA] = fma(k1, src[0], acc[b][1 % NA]);
+                    acc[b][2 % NA] = fma(k2, src[0], acc[b][2 % NA]);
+                    acc[b][3 % NA] = fma(k3, src[0], acc[b][3 % NA]);
+                } else {
+                    // transpose of the P2P: K0 even, K1 odd in the offset
+                    double a = fma(k0, src[0], acc[b][0]);
+                    a = fma(-k1, src[1], a);
+                    a = fma(-k2, src[2], a);
+                    acc[b][0] = fma(-k3, src[3], a);
+                }
+            }
+        }
+    }
+
+    if (p.L >= 1) {
+        const DevLevel &D = p.lev[p.L - 1];
+        const int bQ = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
+        const int64_t np = D.np;
+        const int64_t np3 = np * np * np;
+        const int64_t q = (((int64_t)(Qz >> 1)) * np + (Qy >> 1)) * np + (Qx >> 1);
+        double C[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) C[k] = D.C[(k * 8 + bQ) * np3 + q];
+        const double hh = 0.5 * p.hleaf;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            double e[NC];
+            taylor((b & 1) ? hh : -hh, ((b >> 1) & 1) ? hh : -hh, (b >> 2) ? hh : -hh, e);  // e(z_leaf - z_Q)
+            double ph = 0.0;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) ph = fma(e[k], C[k], ph);
+            acc[b][0] += ph;
+            if constexpr (!ADJ) {
+                double gr[3] = {0.0, 0.0, 0.0};
+                grad_apply(gr, e, C);
+                acc[b][1 % NA] -= gr[0];
+                acc[b][2 % NA] -= gr[1];
+                acc[b][3 % NA] -= gr[2];
+            }
+        }
+    }
+
+    const int sgx = Qx >> 2, sgy = Qy >> 2, sgz = Qz >> 2;
+    const int64_t base = (int64_t)p.leaf_slot[((int64_t)sgz * p.sL + sgy) * p.sL + sgx] * 512;
+    const int lx0 = (2 * Qx) & 7, ly0 = (2 * Qy) & 7, lz0 = (2 * Qz) & 7;
+    const int64_t N = p.n_leaf_cells;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int64_t idx = base + ((lz0 + (b >> 2)) * 8 + (ly0 + ((b >> 1) & 1))) * 8 + (lx0 + (b & 1));
+        if constexpr (!ADJ) {
+            out0[idx] = acc[b][0];
+            out1[idx] = acc[b][1 % NA];
+            out1[N + idx] = acc[b][2 % NA];
+            out1[2 * N + idx] = acc[b][3 % NA];
+        } else {
+            out0[idx] = p.h3 * acc[b][0];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+static inline unsigned grid_for(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
+
+hipError_t launch_upward_leaf(const DevPlan &p, const double *rho, hipStream_t s)
+{
+    const int64_t n = (int64_t)p.npL * p.npL * p.npL;
+    hipLaunchKernelGGL(k_upward_leaf<false>, dim3(grid_for(n)), dim3(WG), 0, s, p, rho, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const double *u, hipStream_t s)
+{
+    const int64_t n = (int64_t)p.npL * p.npL * p.npL;
+    hipLaunchKernelGGL(k_upward_leaf<true>, dim3(grid_for(n)), dim3(WG), 0, s, p, w, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2m(const DevPlan &p, int l, hipStream_t s)
+{
+    const int64_t n = 2 * (int64_t)p.lev[l].np;
+    hipLaunchKernelGGL(k_m2m, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2l(const DevPlan &p, hipStream_t s)
+{
+    if (p.n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_m2l, dim3(p.n_items), dim3(WG), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_root_reduce(const DevPlan &p, hipStream_t s)
+{
+    if (p.n_root_parts == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_root_reduce, dim3(grid_for(NC * 8 * 64)), dim3(WG), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2l(const DevPlan &p, int l, hipStream_t s)
+{
+    const int64_t n = 2 * (int64_t)p.lev[l].np;
+    hipLaunchKernelGGL(k_l2l, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s)
+{
+    const Block bs = block_shape(p.npL);
+    const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
+    hipLaunchKernelGGL(k_leaf<false>, dim3((unsigned)((nblk + 3) / 4)), dim3(WG), 0, s, p, phi, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s)
+{
+    const Block bs = block_shape(p.npL);
+    const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
+    hipLaunchKernelGGL(k_leaf<true>, dim3((unsigned)((nblk + 3) / 4)), dim3(WG), 0, s, p, drho, nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace otfmm

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Tolerance: the FP64 path must match the oracle FMM (same theta, order and
+tree) to 1e-12 normwise, i.e. max|d phi| / max|phi| and the same for g with
+the per-cell Euclidean norm (rounding-order differences only: ~650 terms per
+cell at 1.1e-16 each).  At the 128^3 size the oracle is evaluated per sink on
+a sample of cells; properties that hold at any size (momentum conservation,
+the adjoint identities) are checked on the whole grid.
+"""
+import numpy as np
+import pytest
+
+from conftest import normwise, normwise_vec
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle as O  # noqa: E402
+from paper_2412_15518_amd import fmm, workloads as W  # noqa: E402
+
+TOL = 1e-12
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fmm.load_library()
+    torch.cuda.set_device(0)
+
+
+def to_dev(layout, dense):
+    return torch.from_numpy(layout.dense_to_layout(np.ascontiguousarray(dense))).cuda()
+
+
+def gpu_forward(layout, rho, theta=0.4, plan=None):
+    plan = plan or fmm.Plan(layout, theta=theta)
+    say("forward", layout.depth, "theta", theta)
+    phi, g = plan.forward(to_dev(layout, rho))
+    torch.cuda.synchronize()
+    return layout.layout_to_dense(phi.cpu().numpy()), layout.layout_to_dense(g.cpu().numpy())
+
+
+def gpu_adjoint(layout, w, u, theta=0.4, plan=None):
+    plan = plan or fmm.Plan(layout, theta=theta)
+    say("adjoint", layout.depth, "theta", theta)
+    dr = plan.adjoint(to_dev(layout, w), to_dev(layout, u))
+    torch.cuda.synchronize()
+    return layout.layout_to_dense(dr.cpu().numpy())
+
+
+# ------------------------------------------------------------------ forward
+@pytest.mark.parametrize("kind,seed", [("uniform", 1), ("signed", 2), ("sparse", 3)])
+def test_single_subgrid_equals_direct_sum(kind, seed):
+    lay = W.uniform_layout(0)
+    rho = W.random_density(8, seed, kind)
+    phi, g = gpu_forward(lay, rho)
+    pd, gd = O.direct(rho)
+    assert normwise(phi, pd) < TOL
+    assert normwise_vec(g, gd) < TOL
+
+
+@pytest.mark.parametrize("L,order,seed", [(1, "lex", 11), (1, "random", 12), (2, "morton", 13), (2, "random", 14)])
+def test_forward_matches_oracle_small(L, order, seed):
+    lay = W.uniform_layout(L, order=order, seed=seed)
+    n = 8 << L
+    rho = W.random_density(n, seed, "uniform")
+    phi, g = gpu_forward(lay, rho)
+    po, go = O.fmm(rho)
+    assert normwise(phi, po) < TOL
+    assert normwise_vec(g, go) < TOL
+
+
+@pytest.mark.parametrize("theta", [0.34, 0.5, 0.7, 1.0])
+def test_forward_other_theta(theta):
+    lay = W.uniform_layout(2)
+    rho = W.random_density(32, 21, "signed")
+    phi, g = gpu_forward(lay, rho, theta=theta)
+    po, go = O.fmm(rho, theta=theta)
+    assert normwise(phi, po) < TOL
+    assert normwise_vec(g, go) < TOL
+
+
+def test_forward_scaled_units():
+    lay = W.uniform_layout(2)
+    lay.h_leaf_min = 0.37
+    lay.G = 2.5
+    rho = W.random_density(32, 22, "uniform")
+    phi, g = gpu_forward(lay, rho)
+    po, go = O.fmm(rho, h=0.37, G=2.5)
+    assert normwise(phi, po) < TOL
+    assert normwise_vec(g, go) < TOL
+
+
+def test_cfg1_sphere():
+    """32^3 uniform sphere: GPU == oracle FMM; accuracy against the direct sum
+    is the method's (stated, ~1e-4 in phi, ~3e-3 in g)."""
+    cfg = W.cfg1_sphere()
+    lay = W.uniform_layout(cfg["L"])
+    phi, g = gpu_forward(lay, cfg["rho"])
+    po, go = O.fmm(cfg["rho"])
+    assert normwise(phi, po) < TOL
+    assert normwise_vec(g, go) < TOL
+    pd, gd = O.direct(cfg["rho"])
+    ep, eg = normwise(phi, pd), normwise_vec(g, gd)
+    say(f"cfg1 vs direct sum: phi {ep:.3e}  g {eg:.3e}")
+    assert ep < 2e-4 and eg < 5e-3
+
+
+def test_cfg5_forward():
+    cfg = W.cfg5_lognormal()
+    lay = W.uniform_layout(cfg["L"], order="morton")
+    phi, g = gpu_forward(lay, cfg["rho"])
+    po, go = O.fmm(cfg["rho"])
+    assert normwise(phi, po) < TOL
+    assert normwise_vec(g, go) < TOL
+
+
+def test_edge_cases_zero_and_point():
+    lay = W.uniform_layout(2)
+    phi, g = gpu_forward(lay, np.zeros((32, 32, 32)))
+    assert not phi.any() and not g.any()
+    rho = np.zeros((32, 32, 32))
+    rho[0, 0, 0] = 1.0          # corner cell
+    rho[31, 17, 5] = -2.0
+    phi, g = gpu_forward(lay, rho)
+    po, go = O.fmm(rho)
+    assert normwise(phi, po) < TOL
+    assert normwise_vec(g, go) < TOL
+
+
+def test_cfg2_sampled_full_size():
+    """128^3 two-polytrope workload, one forward as the benchmark runs it;
+    oracle evaluated per sink on 512 sampled cells (plus the domain corners)."""
+    cfg = W.cfg2_two_polytropes(with_cotangents=False)
+    lay = W.uniform_layout(cfg["L"])
+    phi, g = gpu_forward(lay, cfg["rho"])
+    rng = np.random.default_rng(2024)
+    n = 128
+    sinks = np.concatenate([rng.choice(n ** 3, 512, replace=False),
+                            [0, n - 1, n * n - 1, n ** 3 - 1, (64 * n + 64) * n + 39]]).astype(np.int64)
+    say("oracle sinks", sinks.size)
+    po, go = O.fmm_sinks(cfg["rho"], sinks)
+    ph = phi.reshape(-1)[sinks]
+    gg = g.reshape(3, -1)[:, sinks]
+    assert np.abs(ph - po).max() / np.abs(phi).max() < TOL
+    assert np.sqrt(((gg - go) ** 2).sum(0)).max() / np.sqrt((g ** 2).sum(0)).max() < TOL
+    # whole-grid property: Newton's third law
+    F = (cfg["rho"][None] * g).reshape(3, -1).sum(1)
+    assert np.abs(F).max() / np.abs(cfg["rho"][None] * g).sum() < 1e-12
+
+
+def test_deterministic_bitwise():
+    cfg = W.cfg5_lognormal()
+    lay = W.uniform_layout(cfg["L"])
+    plan = fmm.Plan(lay)
+    r = to_dev(lay, cfg["rho"])
+    a = plan.forward(r)
+    b = plan.forward(r)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    w, u = to_dev(lay, cfg["w"]), to_dev(lay, cfg["u"])
+    assert torch.equal(plan.adjoint(w, u), plan.adjoint(w, u))
+
+
+# ------------------------------------------------------------------ adjoint
+@pytest.mark.parametrize("L", [0, 1, 2])
+def test_adjoint_matches_oracle_small(L):
+    n = 8 << L
+    rng = np.random.default_rng(300 + L)
+    w = rng.standard_normal((n, n, n))
+    u = rng.standard_normal((3, n, n, n))
+    lay = W.uniform_layout(L, order="random", seed=L)
+    dr = gpu_adjoint(lay, w, u)
+    do = O.fmm_adjoint(w, u)
+    assert normwise(dr, do) < TOL
+
+
+def test_adjoint_cfg5_matches_oracle_and_fd():
+    cfg = W.cfg5_lognormal()
+    lay = W.uniform_layout(cfg["L"])
+    plan = fmm.Plan(lay)
+    dr = gpu_adjoint(lay, cfg["w"], cfg["u"], plan=plan)
+    do = O.fmm_adjoint(cfg["w"], cfg["u"])
+    assert normwise(dr, do) < TOL
+    # central finite differences of L = sum w phi + sum u g through the GPU forward
+    rho = to_dev(lay, cfg["rho"])
+    w = to_dev(lay, cfg["w"])
+    u = to_dev(lay, cfg["u"]).reshape(3, -1)
+    pos = np.argsort(lay._leaf_index())          # dense index -> layout position
+    eps = 1e-6
+    fd, ad = [], []
+    say("finite differences", len(cfg["cells"]))
+    for j in cfg["cells"]:
+        k = int(pos[j])
+        vals = []
+        for sgn in (1.0, -1.0):
+            r = rho.clone()
+            r[k] += sgn * eps
+            ph, g = plan.forward(r)
+            vals.append(float((w * ph).sum() + (u * g).sum()))
+        fd.append((vals[0] - vals[1]) / (2 * eps))
+        ad.append(dr.reshape(-1)[j])
+    fd, ad = np.array(fd), np.array(ad)
+    err = np.abs(fd - ad).max() / np.abs(ad).max()
+    say(f"FD vs adjoint (eps=1e-6, 64 cells): {err:.3e}")
+    assert err < 1e-5
+
+
+def test_adjoint_identities_full_size():
+    """128^3: dot-product identity and, for u = 0, the adjoint equals the
+    forward potential of w (the potential operator is symmetric)."""
+    cfg = W.cfg2_two_polytropes()
+    lay = W.uniform_layout(cfg["L"])
+    plan = fmm.Plan(lay)
+    rho, w, u = to_dev(lay, cfg["rho"]), to_dev(lay, cfg["w"]), to_dev(lay, cfg["u"])
+    say("128^3 forward + adjoint")
+    phi, g = plan.forward(rho)
+    dr = plan.adjoint(w, u)
+    lhs = float((w * phi).sum() + (u.reshape(3, -1) * g).sum())
+    rhs = float((dr * rho).sum())
+    scale = float((w * phi).abs().sum() + (u.reshape(3, -1) * g).abs().sum())
+    assert abs(lhs - rhs) / scale < 1e-12
+    d0 = plan.adjoint(w, torch.zeros_like(u))
+    pw, _ = plan.forward(w)
+    assert float((d0 - pw).abs().max() / pw.abs().max()) < TOL
+
+
+def test_autograd_function():
+    lay = W.uniform_layout(1)
+    plan = fmm.Plan(lay)
+    rng = np.random.default_rng(5)
+    rho = to_dev(lay, rng.uniform(size=(16, 16, 16))).requires_grad_(True)
+    w = to_dev(lay, rng.standard_normal((16, 16, 16)))
+    u = to_dev(lay, rng.standard_normal((3, 16, 16, 16))).reshape(3, -1)
+    phi, g = fmm.otfmm(rho, plan)
+    loss = (w * phi).sum() + (u * g).sum()
+    (grad,) = torch.autograd.grad(loss, rho)
+    ref = plan.adjoint(w, u)
+    assert torch.allclose(grad, ref, rtol=0, atol=0)
+
+
+def test_timing_api():
+    lay = W.uniform_layout(2)
+    plan = fmm.Plan(lay)
+    r = to_dev(lay, W.random_density(32, 3))
+    plan.timing_begin(4)
+    for _ in range(3):
+        plan.forward(r)
+    plan.adjoint(r, torch.zeros((3, r.numel()), dtype=torch.float64, device=r.device))
+    t = plan.timing_end()
+    assert t["calls"] == 4
+    assert t["phases"]["m2l"]["events"] == 4 and t["phases"]["m2l"]["ms"] > 0
+    assert t["phases"]["leaf"]["events"] == 3 and t["phases"]["leaf_adj"]["events"] == 1
+    assert t["phases"]["total"]["events"] == 4
+
+
+def test_bad_tensor_arguments_raise():
+    lay = W.uniform_layout(1)
+    plan = fmm.Plan(lay)
+    with pytest.raises(TypeError):
+        plan.forward(torch.zeros(16 ** 3, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.forward(torch.zeros(100, dtype=torch.float64, device="cuda"))
