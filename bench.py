@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-slab", type=int, default=16,
                     help="leaf z-layers of the 128^3 grid in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before warmup, copy this many MiB device to device once: a plain copy "
+                         "kernel of known traffic that calibrates HBM counter readings")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -101,6 +104,16 @@ def main():
     phi = torch.empty(N, dtype=torch.float64, device="cuda")
     g = torch.empty((3, N), dtype=torch.float64, device="cuda")
     drho = torch.empty(N, dtype=torch.float64, device="cuda")
+
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_mib} MiB")
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
