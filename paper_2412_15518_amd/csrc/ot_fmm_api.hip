@@ -220,6 +220,16 @@ void build_tables(ot_fmm_plan P)
                 K[1] = c * x; K[2] = c * y; K[3] = c * z;
             }
 
+    // the leaf pass reads, per parent offset P of its list, the 27 rows 2P + e
+    const std::vector<char4> &pl = (L == 0) ? P->plist_cube : P->plist_near;
+    P->Kst.assign(pl.size() * 27 * 4, 0.0);
+    for (size_t i = 0; i < pl.size(); ++i)
+        for (int e = 0; e < 27; ++e) {
+            const int ox = 2 * pl[i].x + e % 3 - 1, oy = 2 * pl[i].y + (e / 3) % 3 - 1, oz = 2 * pl[i].z + e / 9 - 1;
+            for (int j = 0; j < 4; ++j)
+                P->Kst[(i * 27 + e) * 4 + j] = P->Ktab[(size_t)off_index(ox, oy, oz) * 4 + j];
+        }
+
     // derivative tensors per level l < L at R = z_sink - z_source = -o h_l
     const int nlev = std::max(L, 1);
     P->Dtab.assign((size_t)nlev * OFF_N * NC, 0.0);
@@ -394,6 +404,7 @@ int setup_device(ot_fmm_plan P)
     int rc;
     if ((rc = dev_upload(P, &d.leaf_slot, P->leaf_slot))) return rc;
     if ((rc = dev_upload(P, &d.Ktab, P->Ktab))) return rc;
+    if ((rc = dev_upload(P, &d.Kst, P->Kst))) return rc;
     if ((rc = dev_upload(P, &d.Dtab, P->Dtab))) return rc;
     if ((rc = dev_upload(P, &d.plist_near, P->plist_near))) return rc;
     if ((rc = dev_upload(P, &d.plist_cube, P->plist_cube))) return rc;

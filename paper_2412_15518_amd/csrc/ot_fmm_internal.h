@@ -67,6 +67,7 @@ struct DevPlan {
     const int32_t *leaf_slot;   // [sL^3] leaf index in layout order
     double *src;                // [4][8][ppL^3]
     const double *Ktab;         // [OFF_N][4]: K0, K1x, K1y, K1z of a leaf pair
+    const double *Kst;          // [n_plist_leaf][27][4]: Ktab rows of 2P + e, e in {-1,0,1}^3
     const double *Dtab;         // [L][OFF_N][NC]: derivative tensor of -G/r per level
     const char4 *plist_leaf; int n_plist_leaf;   // parent offsets of the leaf P2P
     const char4 *plist_near; int n_plist_near;   // |P| <= 1/theta (levels >= 1)
@@ -103,7 +104,7 @@ struct ot_fmm_plan_s {
     std::vector<int32_t> leaf_slot;
     std::vector<char4> plist_near, plist_cube;
     std::vector<otfmm::M2LItem> items;
-    std::vector<double> Ktab, Dtab;
+    std::vector<double> Ktab, Kst, Dtab;
     ot_fmm_info info{};
 
     // device state

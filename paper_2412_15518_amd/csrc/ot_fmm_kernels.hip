@@ -287,13 +287,37 @@ __global__ __launch_bounds__(WG) void k_m2m(const DevPlan p, int l)
 }
 
 // ------------------------------------------------------------------------
-// M2L, every level below the leaves in one launch.  Workgroup = one work
-// item (64 sink parents x one range of parent offsets); wave w handles the
-// sink children b = 2w and 2w+1 of its lane's parent.
+// M2L, every level below the leaves in one launch.
+//
+// Workgroup = one work item: 64 sink parents of one level (lane = parent)
+// and a range of parent offsets P; wave w handles the sink children
+// b = 2w and 2w+1.  All four waves need the same source moments (the
+// children of q + P), so the source tile of two source children (2 x 20
+// components x 64 parents, 20 KB) is loaded once per workgroup -- each wave
+// fetches a quarter of the components of its lane's own source parent --
+// and shared through LDS, double-buffered: the next tile is loaded into
+// registers while the current one is consumed.
+//
+// Items are assigned so that each XCD walks a contiguous run of them
+// (workgroups are dealt round-robin to the 8 XCDs), which keeps the
+// neighbouring blocks that share source halos on one L2.
 // ------------------------------------------------------------------------
+constexpr int M2L_TBP = 2;                       // source children per tile
+constexpr int M2L_TILE = M2L_TBP * NC;           // (child, component) rows per tile
+constexpr int M2L_PER_WAVE = M2L_TILE / 4;       // rows each wave stages
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks)
+{
+    const int per = (nblocks + 7) >> 3;          // items per XCD
+    return (bid & 7) * per + (bid >> 3);
+}
+
 __global__ __launch_bounds__(WG) void k_m2l(const DevPlan p)
 {
-    const M2LItem it = p.items[blockIdx.x];
+    __shared__ double tile[2][M2L_TILE][64];
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= p.n_items) return;
+    const M2LItem it = p.items[item];
     const int lev = it.level;
     const DevLevel &D = p.lev[lev];
     const int lane = threadIdx.x & 63;
@@ -309,20 +333,46 @@ __global__ __launch_bounds__(WG) void k_m2l(const DevPlan p)
     const double *__restrict__ Dl = p.Dtab + (size_t)lev * OFF_N * NC;
     const char4 *plist = lev == 0 ? p.plist_cube : p.plist_near;
     const int r2i = p.r2i;
+    const int ntiles = (it.pend - it.pbeg) * (8 / M2L_TBP);
+
+    // stage tile t: rows r = wave + 4 j (child bp0 + r / NC, component r % NC)
+    auto fetch = [&](int t, double *reg) {
+        const char4 P = plist[it.pbeg + t / (8 / M2L_TBP)];
+        const int bp0 = (t % (8 / M2L_TBP)) * M2L_TBP;
+        const int64_t poff = ((int64_t)P.z * pp + P.y) * pp + P.x;
+#pragma unroll
+        for (int j = 0; j < M2L_PER_WAVE; ++j) {
+            const int r = wave + 4 * j;
+            const int k = r % NC, bp = bp0 + r / NC;
+            reg[j] = Mb[(k * 8 + bp) * pp3 + poff];
+        }
+    };
+    auto stash = [&](int buf, const double *reg) {
+#pragma unroll
+        for (int j = 0; j < M2L_PER_WAVE; ++j) tile[buf][wave + 4 * j][lane] = reg[j];
+    };
 
     double C0[NC], C1[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) { C0[k] = 0.0; C1[k] = 0.0; }
 
-    for (int pi = it.pbeg; pi < it.pend; ++pi) {
-        const char4 P = plist[pi];
-        const int64_t poff = ((int64_t)P.z * pp + P.y) * pp + P.x;
-#pragma unroll 1
-        for (int bp = 0; bp < 8; ++bp) {
+    double reg[M2L_PER_WAVE];
+    fetch(0, reg);
+    stash(0, reg);
+    __syncthreads();
+
+    for (int t = 0; t < ntiles; ++t) {
+        if (t + 1 < ntiles) fetch(t + 1, reg);
+        const int buf = t & 1;
+        const char4 P = plist[it.pbeg + t / (8 / M2L_TBP)];
+        const int bp0 = (t % (8 / M2L_TBP)) * M2L_TBP;
+#pragma unroll
+        for (int i = 0; i < M2L_TBP; ++i) {
+            const int bp = bp0 + i;
+            const int sx = 2 * P.x + (bp & 1), sy = 2 * P.y + ((bp >> 1) & 1), sz = 2 * P.z + (bp >> 2);
             double Ms[NC];
 #pragma unroll
-            for (int k = 0; k < NC; ++k) Ms[k] = Mb[(k * 8 + bp) * pp3 + poff];
-            const int sx = 2 * P.x + (bp & 1), sy = 2 * P.y + ((bp >> 1) & 1), sz = 2 * P.z + (bp >> 2);
+            for (int k = 0; k < NC; ++k) Ms[k] = tile[buf][i * NC + k][lane];
             {
                 const int ox = sx - (b0 & 1), oy = sy - ((b0 >> 1) & 1), oz = sz - (b0 >> 2);
                 if (ox * ox + oy * oy + oz * oz > r2i) {
@@ -344,6 +394,8 @@ __global__ __launch_bounds__(WG) void k_m2l(const DevPlan p)
                 }
             }
         }
+        if (t + 1 < ntiles) stash(buf ^ 1, reg);
+        __syncthreads();
     }
 
     const int64_t np = D.np;
@@ -411,7 +463,12 @@ __global__ __launch_bounds__(WG) void k_l2l(const DevPlan p, int l)
 
 // ------------------------------------------------------------------------
 // Leaf pass: P2P over the leaf stencil + L2L/L2P from level L-1.
-// A wave owns 64 leaf parents Q (lane = Q) and all 8 children of each.
+// A wave owns 64 leaf parents Q (lane = Q) and all 8 children of each.  For
+// a parent offset P the 64 child pairs (b', b) use the 27 offsets
+// 2P + e, e = b' - b in {-1,0,1}^3; Kst holds, per entry of the parent-offset
+// list, those 27 rows of (K0, K1x, K1y, K1z), so each row is one scalar load
+// at a constant offset and serves every pair with that e.  The sources of the
+// next P are loaded while the current ones are consumed.
 // ------------------------------------------------------------------------
 template <bool ADJ>
 __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, double *__restrict__ out0,
@@ -420,7 +477,7 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, double *__restrict
     const int npL = p.npL;
     const Block bs = block_shape(npL);
     const int nbx = npL / bs.bx, nby = npL / bs.by, nbz = npL / bs.bz;
-    const int blk = blockIdx.x * (WG / 64) + uniform(threadIdx.x >> 6);
+    const int blk = xcd_remap(blockIdx.x, gridDim.x) * (WG / 64) + uniform(threadIdx.x >> 6);
     if (blk >= nbx * nby * nbz) return;
     const int lane = threadIdx.x & 63;
     const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
@@ -430,57 +487,69 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, double *__restrict
     const int64_t ppL3 = pp * pp * pp;
     const double *__restrict__ S = p.src + ((Qz + p.hpL) * pp + (Qy + p.hpL)) * pp + (Qx + p.hpL);
 
-    // forward: phi, g_x, g_y, g_z per sink child; adjoint: one sum per sink child
-    constexpr int NA = ADJ ? 1 : 4;
+    constexpr int NA = ADJ ? 1 : 4;     // accumulators per sink child
+    constexpr int NS = ADJ ? 4 : 1;     // source planes
     double acc[8][NA];
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
         for (int j = 0; j < NA; ++j) acc[b][j] = 0.0;
 
-    for (int pi = 0; pi < p.n_plist_leaf; ++pi) {
+    auto fetch = [&](int pi, double (*dst)[NS]) {
         const char4 P = p.plist_leaf[pi];
         const int64_t poff = ((int64_t)P.z * pp + P.y) * pp + P.x;
-#pragma unroll 1
-        for (int bp = 0; bp < 8; ++bp) {
-            const int sx = 2 * P.x + (bp & 1), sy = 2 * P.y + ((bp >> 1) & 1), sz = 2 * P.z + (bp >> 2);
-            double src[4];
-            if constexpr (!ADJ) {
-                src[0] = S[bp * ppL3 + poff];
-            } else {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) src[j] = S[(j * 8 + bp) * ppL3 + poff];
-            }
+        for (int bp = 0; bp < 8; ++bp)
+#pragma unroll
+            for (int j = 0; j < NS; ++j) dst[bp][j] = S[(j * 8 + bp) * ppL3 + poff];
+    };
+
+    const int np = p.n_plist_leaf;
+    double cur[8][NS], nxt[8][NS];
+    fetch(0, cur);
+    for (int pi = 0; pi < np; ++pi) {
+        if (pi + 1 < np) fetch(pi + 1, nxt);
+        const double *__restrict__ Kp = p.Kst + (size_t)pi * 27 * 4;
+#pragma unroll
+        for (int e = 0; e < 27; ++e) {
+            const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+            const double k0 = Kp[4 * e], k1 = Kp[4 * e + 1], k2 = Kp[4 * e + 2], k3 = Kp[4 * e + 3];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                const int ox = sx - (b & 1), oy = sy - ((b >> 1) & 1), oz = sz - (b >> 2);
-                const double *K = p.Ktab + off_index(ox, oy, oz) * 4;
-                const double k0 = K[0], k1 = K[1], k2 = K[2], k3 = K[3];
+                const int bx = (b & 1) + ex, by = ((b >> 1) & 1) + ey, bz = (b >> 2) + ez;
+                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                const int bp = bx + 2 * by + 4 * bz;
                 if constexpr (!ADJ) {
-                    acc[b][0] = fma(k0, src[0], acc[b][0]);
-                    acc[b][1 % NA] = fma(k1, src[0], acc[b][1 % NA]);
-                    acc[b][2 % NA] = fma(k2, src[0], acc[b][2 % NA]);
-                    acc[b][3 % NA] = fma(k3, src[0], acc[b][3 % NA]);
+                    acc[b][0] = fma(k0, cur[bp][0], acc[b][0]);
+                    acc[b][1 % NA] = fma(k1, cur[bp][0], acc[b][1 % NA]);
+                    acc[b][2 % NA] = fma(k2, cur[bp][0], acc[b][2 % NA]);
+                    acc[b][3 % NA] = fma(k3, cur[bp][0], acc[b][3 % NA]);
                 } else {
                     // transpose of the P2P: K0 even, K1 odd in the offset
-                    double a = fma(k0, src[0], acc[b][0]);
-                    a = fma(-k1, src[1], a);
-                    a = fma(-k2, src[2], a);
-                    acc[b][0] = fma(-k3, src[3], a);
+                    double a = fma(k0, cur[bp][0], acc[b][0]);
+                    a = fma(-k1, cur[bp][1 % NS], a);
+                    a = fma(-k2, cur[bp][2 % NS], a);
+                    acc[b][0] = fma(-k3, cur[bp][3 % NS], a);
                 }
             }
+        }
+        if (pi + 1 < np) {
+#pragma unroll
+            for (int bp = 0; bp < 8; ++bp)
+#pragma unroll
+                for (int j = 0; j < NS; ++j) cur[bp][j] = nxt[bp][j];
         }
     }
 
     if (p.L >= 1) {
         const DevLevel &D = p.lev[p.L - 1];
         const int bQ = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
-        const int64_t np = D.np;
-        const int64_t np3 = np * np * np;
-        const int64_t q = (((int64_t)(Qz >> 1)) * np + (Qy >> 1)) * np + (Qx >> 1);
+        const int64_t nq = D.np;
+        const int64_t nq3 = nq * nq * nq;
+        const int64_t q = (((int64_t)(Qz >> 1)) * nq + (Qy >> 1)) * nq + (Qx >> 1);
         double C[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) C[k] = D.C[(k * 8 + bQ) * np3 + q];
+        for (int k = 0; k < NC; ++k) C[k] = D.C[(k * 8 + bQ) * nq3 + q];
         const double hh = 0.5 * p.hleaf;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -547,7 +616,8 @@ hipError_t launch_m2m(const DevPlan &p, int l, hipStream_t s)
 hipError_t launch_m2l(const DevPlan &p, hipStream_t s)
 {
     if (p.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_m2l, dim3(p.n_items), dim3(WG), 0, s, p);
+    const unsigned grid = (unsigned)(((p.n_items + 7) / 8) * 8);     // whole rounds over the 8 XCDs
+    hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(WG), 0, s, p);
     return hipGetLastError();
 }
 
@@ -569,7 +639,8 @@ hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s)
 {
     const Block bs = block_shape(p.npL);
     const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
-    hipLaunchKernelGGL(k_leaf<false>, dim3((unsigned)((nblk + 3) / 4)), dim3(WG), 0, s, p, phi, g);
+    const unsigned grid = (unsigned)((((nblk + 3) / 4) + 7) / 8 * 8);   // whole rounds over the 8 XCDs
+    hipLaunchKernelGGL(k_leaf<false>, dim3(grid), dim3(WG), 0, s, p, phi, g);
     return hipGetLastError();
 }
 
@@ -577,7 +648,8 @@ hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s)
 {
     const Block bs = block_shape(p.npL);
     const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
-    hipLaunchKernelGGL(k_leaf<true>, dim3((unsigned)((nblk + 3) / 4)), dim3(WG), 0, s, p, drho, nullptr);
+    const unsigned grid = (unsigned)((((nblk + 3) / 4) + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_leaf<true>, dim3(grid), dim3(WG), 0, s, p, drho, nullptr);
     return hipGetLastError();
 }
 
