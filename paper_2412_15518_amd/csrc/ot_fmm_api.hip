@@ -244,36 +244,58 @@ void build_tables(ot_fmm_plan P)
                 }
     }
 
-    // M2L work items: deepest level first, the root's chunks last
-    P->items.clear();
-    for (int l = L - 1; l >= 1; --l) {
-        const int np = 4 << l;
-        const int bx = std::min(np, 64), by = std::min(np, 64 / bx), bz = 64 / (bx * by);
-        for (int z = 0; z < np; z += bz)
-            for (int y = 0; y < np; y += by)
-                for (int x = 0; x < np; x += bx) {
-                    M2LItem it{};
-                    it.level = l;
-                    it.q0[0] = x; it.q0[1] = y; it.q0[2] = z;
-                    it.pbeg = 0;
-                    it.pend = (int)P->plist_near.size();
-                    it.part = -1;
-                    P->items.push_back(it);
-                }
+}
+
+// Cut each level's M2L units into runs, G workgroups in all, in proportion
+// to the level's units (at least one run per level), and record per level how
+// many partial sums a block can receive.
+void build_m2l_schedule(ot_fmm_plan P, int G)
+{
+    P->mdesc.clear();
+    const int L = P->L;
+    for (int l = 0; l < MAX_LEVELS; ++l) P->dp.lev[l].maxp = 0;
+    if (L < 1) return;
+    std::vector<int64_t> U(L);
+    int64_t Utot = 0;
+    for (int l = 0; l < L; ++l) {
+        const int64_t nblocks = (int64_t)(4 << l) * (4 << l) * (4 << l) / 64;
+        const int nP = (l == 0) ? (int)P->plist_cube.size() : (int)P->plist_near.size();
+        U[l] = nblocks * nP;
+        Utot += U[l];
     }
-    int nparts = 0;
-    if (L >= 1) {
-        const int ncube = (int)P->plist_cube.size();
-        for (int b = 0; b < ncube; b += ROOT_CHUNK) {
-            M2LItem it{};
-            it.level = 0;
-            it.pbeg = b;
-            it.pend = std::min(ncube, b + ROOT_CHUNK);
-            it.part = nparts++;
-            P->items.push_back(it);
+    std::vector<int> Gl(L);
+    int used = 0;
+    for (int l = 0; l < L; ++l) {
+        // at least one run per level, and runs of at least 8 units (32 tiles)
+        Gl[l] = (int)std::max<int64_t>(1, std::min<int64_t>(U[l] / 8, (int64_t)G * U[l] / Utot));
+        used += Gl[l];
+    }
+    // hand any remainder to the deepest level
+    if (used < G) Gl[L - 1] = (int)std::max<int64_t>(1, std::min<int64_t>(U[L - 1] / 8, Gl[L - 1] + (G - used)));
+    for (int l = L - 1; l >= 0; --l) {
+        const int nP = (l == 0) ? (int)P->plist_cube.size() : (int)P->plist_near.size();
+        const int64_t Ul = U[l];
+        const int g = Gl[l];
+        auto run_of = [&](int64_t u) {        // run of this level holding unit u
+            int r = (int)(u * g / Ul);
+            while (r + 1 < g && (int64_t)(r + 1) * Ul / g <= u) ++r;
+            while (r > 0 && (int64_t)r * Ul / g > u) --r;
+            return r;
+        };
+        for (int r = 0; r < g; ++r) {
+            M2LDesc d{};
+            d.level = l;
+            d.ubeg = (int)((int64_t)r * Ul / g);
+            d.uend = (int)((int64_t)(r + 1) * Ul / g);
+            const int64_t first = (int64_t)(d.ubeg / nP) * nP;
+            d.piece0 = (d.ubeg == first) ? 0 : r - run_of(first);
+            P->mdesc.push_back(d);
         }
+        int maxp = 0;
+        for (int64_t b = 0; b < Ul / nP; ++b)
+            maxp = std::max(maxp, run_of(b * nP + nP - 1) - run_of(b * nP) + 1);
+        P->dp.lev[l].maxp = maxp;
     }
-    P->dp.n_root_parts = nparts;
 }
 
 // ordered pairs and algorithmic work of the plan
@@ -408,13 +430,17 @@ int setup_device(ot_fmm_plan P)
     if ((rc = dev_upload(P, &d.Dtab, P->Dtab))) return rc;
     if ((rc = dev_upload(P, &d.plist_near, P->plist_near))) return rc;
     if ((rc = dev_upload(P, &d.plist_cube, P->plist_cube))) return rc;
-    if ((rc = dev_upload(P, &d.items, P->items))) return rc;
+    int ncu = 0, per_cu = 0;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device)) != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute");
+    if ((e = m2l_blocks_per_cu(&per_cu)) != hipSuccess) return hip_fail(e, "occupancy of the M2L kernel");
+    build_m2l_schedule(P, std::max(1, ncu * std::max(1, per_cu)));
+    if ((rc = dev_upload(P, &d.mdesc, P->mdesc))) return rc;
     d.n_plist_near = (int)P->plist_near.size();
     d.n_plist_cube = (int)P->plist_cube.size();
     d.plist_leaf = (L == 0) ? d.plist_cube : d.plist_near;
     d.n_plist_leaf = (L == 0) ? d.n_plist_cube : d.n_plist_near;
-    d.n_items = (int)P->items.size();
-    if ((rc = dev_alloc(P, &d.root_part, (size_t)std::max(d.n_root_parts, 1) * NC * 8 * 64, true))) return rc;
+    d.n_mdesc = (int)P->mdesc.size();
     const size_t ppL3 = (size_t)d.ppL * d.ppL * d.ppL;
     if ((rc = dev_alloc(P, &d.src, 4 * 8 * ppL3, true))) return rc;
     for (int l = 0; l < L; ++l) {
@@ -423,9 +449,16 @@ int setup_device(ot_fmm_plan P)
         v.hp = (l == 0) ? 3 : 2;
         v.pp = v.np + 2 * v.hp;
         v.h = P->h * (double)(1 << (L - l));
+        v.bx = std::min(v.np, 64);
+        v.by = std::min(v.np, 64 / v.bx);
+        v.bz = 64 / (v.bx * v.by);
+        v.nbx = v.np / v.bx;
+        v.nby = v.np / v.by;
         const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;
         if ((rc = dev_alloc(P, &v.M, (size_t)NC * 8 * pp3, true))) return rc;
         if ((rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
+        // pieces a block never receives stay zero: the schedule is fixed per plan
+        if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize after plan setup");

@@ -29,7 +29,6 @@ constexpr int OFF_R = 7;                        // offset tables span [-7, 7]^3
 constexpr int OFF_W = 2 * OFF_R + 1;
 constexpr int OFF_N = OFF_W * OFF_W * OFF_W;    // 3375
 constexpr int MAX_LEVELS = 8;                   // leaf level L <= 7
-constexpr int ROOT_CHUNK = 16;                  // parent offsets per root M2L work item
 constexpr int WG = 256;                         // threads per workgroup (4 waves)
 
 __host__ __device__ inline int off_index(int ox, int oy, int oz)
@@ -41,20 +40,28 @@ struct DevLevel {
     int np;          // parents per axis (n_l / 2)
     int hp;          // halo of the moment array, in parents
     int pp;          // np + 2 hp
-    int pad_;
+    int maxp;        // partial-sum pieces of the M2L per block (see M2LDesc)
+    int bx, by, bz;  // M2L block shape (64 parents)
+    int nbx, nby;    // blocks per axis in x and y
     double h;        // cell width of this level
     double *M;       // [NC][8][pp^3]
-    double *C;       // [NC][8][np^3]
+    double *C;       // [NC][8][np^3] local coefficients (final)
+    double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
 };
 
-// One M2L work item = one workgroup: 64 sink parents of one level (a block
-// of bx*by*bz parents starting at q0) and a range of parent offsets.
-struct M2LItem {
+// M2L work: a block = 64 sink parents of one level (bx*by*bz parents, lane =
+// parent, blocks numbered z-major); a unit = one block and one parent offset
+// P of the level's list (the near list, or the whole cube at the root).  The
+// units of each level are cut into equal runs, one per resident workgroup,
+// and no run crosses a level.  A run [ubeg, uend) (level-local unit indices)
+// starts inside block ubeg / nP; a block split over k runs gets k partial
+// sums, pieces 0..k-1 of the level's Cp: the run holding the block's first
+// unit writes piece 0, the next run piece 1, and so on.  Consumers add the
+// pieces in a fixed order, so the result does not depend on timing.
+struct M2LDesc {
     int level;
-    int q0[3];
-    int pbeg, pend;  // range in the level's parent-offset list
-    int part;        // root partial-sum slot, -1 for levels >= 1
-    int pad_;
+    int ubeg, uend;
+    int piece0;      // piece of the run's first (possibly partial) block
 };
 
 struct DevPlan {
@@ -72,8 +79,7 @@ struct DevPlan {
     const char4 *plist_leaf; int n_plist_leaf;   // parent offsets of the leaf P2P
     const char4 *plist_near; int n_plist_near;   // |P| <= 1/theta (levels >= 1)
     const char4 *plist_cube; int n_plist_cube;   // [-3,3]^3 (root level)
-    const M2LItem *items; int n_items;
-    double *root_part; int n_root_parts;         // [parts][NC][8][64]
+    const M2LDesc *mdesc; int n_mdesc;          // one per M2L workgroup
     DevLevel lev[MAX_LEVELS];
 };
 
@@ -103,7 +109,7 @@ struct ot_fmm_plan_s {
     // host tables
     std::vector<int32_t> leaf_slot;
     std::vector<char4> plist_near, plist_cube;
-    std::vector<otfmm::M2LItem> items;
+    std::vector<otfmm::M2LDesc> mdesc;
     std::vector<double> Ktab, Kst, Dtab;
     ot_fmm_info info{};
 
@@ -121,6 +127,7 @@ hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const doubl
 hipError_t launch_m2m(const DevPlan &p, int level, hipStream_t s);
 hipError_t launch_m2l(const DevPlan &p, hipStream_t s);
 hipError_t launch_root_reduce(const DevPlan &p, hipStream_t s);
+hipError_t m2l_blocks_per_cu(int *n);   // resident M2L workgroups per CU
 hipError_t launch_l2l(const DevPlan &p, int level, hipStream_t s);
 hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s);
 hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s);

@@ -110,6 +110,55 @@ static_assert(make_sub_terms().n == 84, "84 shift terms");
 static_assert(make_dipole_terms().n == 30, "30 dipole terms");
 static_assert(make_grad_terms().n == 30, "30 gradient terms");
 
+// the same 84 terms ordered by source component b: every M[b] is consumed
+// right after it is read, by all sinks at once
+constexpr Terms<84> make_sum_terms_by_source()
+{
+    Terms<84> T{};
+    T.n = 0;
+    for (int b = 0; b < NC; ++b)
+        for (int a = 0; a < NC; ++a)
+            if (order_of(a) + order_of(b) <= 3)
+                T.t[T.n++] = {a, b, comp_of(kMI[a].t + kMI[b].t, kMI[a].u + kMI[b].u, kMI[a].v + kMI[b].v)};
+    return T;
+}
+static_assert(make_sum_terms_by_source().n == 84, "84 terms");
+
+// first term of each source component in the source-major list
+constexpr int source_begin(int b)
+{
+    int n = 0;
+    for (int j = 0; j < b; ++j) n += (order_of(j) == 0) ? 20 : (order_of(j) == 1) ? 10 : (order_of(j) == 2) ? 4 : 1;
+    return n;
+}
+static_assert(source_begin(NC) == 84, "source-major term ranges");
+
+// Two sinks share each source component m = M[b]:
+//   C0[a] += D0[a+b] m,  C1[a] += D1[a+b] m  for the terms of component b
+template <int B, int... I>
+__device__ __forceinline__ void m2l2_component(double *C0, double *C1, const double *D0, const double *D1,
+                                               double m, std::integer_sequence<int, I...>)
+{
+    constexpr Terms<84> T = make_sum_terms_by_source();
+    constexpr int o = source_begin(B);
+    ((C0[T.t[o + I].i] = fma(D0[T.t[o + I].k], m, C0[T.t[o + I].i]),
+      C1[T.t[o + I].i] = fma(D1[T.t[o + I].k], m, C1[T.t[o + I].i])), ...);
+}
+
+// one sink only
+template <int B, int... I>
+__device__ __forceinline__ void m2l1_component(double *C, const double *D, double m, std::integer_sequence<int, I...>)
+{
+    constexpr Terms<84> T = make_sum_terms_by_source();
+    constexpr int o = source_begin(B);
+    ((C[T.t[o + I].i] = fma(D[T.t[o + I].k], m, C[T.t[o + I].i])), ...);
+}
+
+constexpr int terms_of_source(int b)
+{
+    return (order_of(b) == 0) ? 20 : (order_of(b) == 1) ? 10 : (order_of(b) == 2) ? 4 : 1;
+}
+
 // C[a] += D[a+b] M[b] over all 84 terms
 template <int... I>
 __device__ __forceinline__ void m2l_terms(double *C, const double *D, const double *M,
@@ -304,7 +353,6 @@ __global__ __launch_bounds__(WG) void k_m2m(const DevPlan p, int l)
 // ------------------------------------------------------------------------
 constexpr int M2L_TBP = 2;                       // source children per tile
 constexpr int M2L_TILE = M2L_TBP * NC;           // (child, component) rows per tile
-constexpr int M2L_PER_WAVE = M2L_TILE / 4;       // rows each wave stages
 
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
 {
@@ -312,119 +360,186 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
     return (bid & 7) * per + (bid >> 3);
 }
 
-__global__ __launch_bounds__(WG) void k_m2l(const DevPlan p)
+// row[b * 64]: component b of this lane's source in the LDS tile
+template <int... B>
+__device__ __forceinline__ void m2l2_source(double *C0, double *C1, const double *D0, const double *D1,
+                                            const double *row, std::integer_sequence<int, B...>)
 {
-    __shared__ double tile[2][M2L_TILE][64];
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
-    if (item >= p.n_items) return;
-    const M2LItem it = p.items[item];
-    const int lev = it.level;
+    (m2l2_component<B>(C0, C1, D0, D1, row[B * 64], std::make_integer_sequence<int, terms_of_source(B)>{}), ...);
+}
+
+template <int... B>
+__device__ __forceinline__ void m2l1_source(double *C, const double *D, const double *row,
+                                            std::integer_sequence<int, B...>)
+{
+    (m2l1_component<B>(C, D, row[B * 64], std::make_integer_sequence<int, terms_of_source(B)>{}), ...);
+}
+
+// M2L over every level below the leaves in one launch.
+//
+// Exactly one workgroup (8 waves) per resident slot; workgroup g walks its
+// run of units (block, P) of one level in order, 8 / M2L_TBP tiles of M2L_TBP
+// source children per unit.  Wave w handles sink child b = w of its lane's parent,
+// so a lane keeps 20 accumulators and a wave one derivative row (20
+// scalars): few registers, many waves per SIMD to hide the scalar and
+// memory latencies.  The tile of source moments (2 children x 20 components
+// x 64 parents) is loaded once per workgroup -- thread t fetches M2L_TILE/8 of
+// its rows -- and shared through LDS, double-buffered: tile k+1 travels through
+// registers while tile k is consumed, two components per 16-byte LDS read.
+// Sums stay in registers while the block is the same and are stored as a
+// partial sum (piece) when it changes.
+constexpr int M2L_WG = 512;                       // 8 waves, one per sink child
+constexpr int M2L_ROWS_PER_THREAD = M2L_TILE * 64 / M2L_WG;   // rows each thread stages
+
+template <int PAIR, int... I>
+__device__ __forceinline__ void m2l1_pair(double *C, const double *D, double2 m, std::integer_sequence<int, I...>)
+{
+    m2l1_component<2 * PAIR>(C, D, m.x, std::make_integer_sequence<int, terms_of_source(2 * PAIR)>{});
+    m2l1_component<2 * PAIR + 1>(C, D, m.y, std::make_integer_sequence<int, terms_of_source(2 * PAIR + 1)>{});
+}
+
+template <int... PAIR>
+__device__ __forceinline__ void m2l1_child(double *C, const double *D, const double2 *rows, int lane,
+                                           std::integer_sequence<int, PAIR...>)
+{
+    // rows[pair * 64 + lane] = components (2 pair, 2 pair + 1) of the lane's source
+    (m2l1_pair<PAIR>(C, D, rows[PAIR * 64 + lane], std::integer_sequence<int>{}), ...);
+}
+
+__global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *__restrict__ Dtab,
+                                                const char4 *__restrict__ near, const char4 *__restrict__ cube,
+                                                const M2LDesc *__restrict__ descs)
+{
+    // [buffer][child of the tile][component pair][lane] -> 2 components
+    __shared__ double2 tile[2][M2L_TBP][NC / 2][64];
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g >= p.n_mdesc) return;
+    const M2LDesc d = descs[g];
+    const int lev = d.level;
     const DevLevel &D = p.lev[lev];
     const int lane = threadIdx.x & 63;
-    const int wave = uniform(threadIdx.x >> 6);
-    const Block bs = block_shape(D.np);
-    const int qx = it.q0[0] + lane % bs.bx;
-    const int qy = it.q0[1] + (lane / bs.bx) % bs.by;
-    const int qz = it.q0[2] + lane / (bs.bx * bs.by);
-    const int b0 = 2 * wave, b1 = 2 * wave + 1;
-    const int64_t pp = D.pp;
-    const int64_t pp3 = pp * pp * pp;
-    const double *__restrict__ Mb = D.M + ((qz + D.hp) * pp + (qy + D.hp)) * pp + (qx + D.hp);
-    const double *__restrict__ Dl = p.Dtab + (size_t)lev * OFF_N * NC;
-    const char4 *plist = lev == 0 ? p.plist_cube : p.plist_near;
+    const int b = uniform(threadIdx.x >> 6);        // this wave's sink child
     const int r2i = p.r2i;
-    const int ntiles = (it.pend - it.pbeg) * (8 / M2L_TBP);
+    const int nP = lev == 0 ? p.n_plist_cube : p.n_plist_near;
+    const char4 *__restrict__ plist = lev == 0 ? cube : near;
+    const double *__restrict__ Dl = Dtab + (size_t)lev * OFF_N * NC;
+    const int np = D.np, pp = D.pp, hp = D.hp;
+    const int pp3 = pp * pp * pp, np3 = np * np * np;
+    const int lx = lane & (D.bx - 1), ly = (lane / D.bx) & (D.by - 1), lz = lane / (D.bx * D.by);
+    auto lane_xyz = [&](int blk, int &qx, int &qy, int &qz) {
+        qx = (blk % D.nbx) * D.bx + lx;
+        qy = ((blk / D.nbx) % D.nby) * D.by + ly;
+        qz = (blk / (D.nbx * D.nby)) * D.bz + lz;
+    };
+    auto lane_q = [&](int blk) {
+        int qx, qy, qz;
+        lane_xyz(blk, qx, qy, qz);
+        return (qz * np + qy) * np + qx;
+    };
+    auto lane_mq = [&](int blk) {
+        int qx, qy, qz;
+        lane_xyz(blk, qx, qy, qz);
+        return ((qz + hp) * pp + (qy + hp)) * pp + (qx + hp);
+    };
+    constexpr int TPP = 8 / M2L_TBP;                // tiles per unit
+    static_assert(M2L_TILE % 8 == 0, "each wave stages the same number of rows");
+    const int ntiles = (d.uend - d.ubeg) * TPP;
 
-    // stage tile t: rows r = wave + 4 j (child bp0 + r / NC, component r % NC)
-    auto fetch = [&](int t, double *reg) {
-        const char4 P = plist[it.pbeg + t / (8 / M2L_TBP)];
-        const int bp0 = (t % (8 / M2L_TBP)) * M2L_TBP;
-        const int64_t poff = ((int64_t)P.z * pp + P.y) * pp + P.x;
+    // fetch cursor: block fb, parent offset fi, tile ft.  Thread (wave w, lane)
+    // stages rows r = w + 8 j: component r % 20 of tile child r / 20
+    int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
+    int fmq = lane_mq(fb);
+    auto fetch = [&](double *reg) {
+        const char4 P = plist[fi];
+        const double *src = D.M + (fmq + ft * M2L_TBP * pp3 + (P.z * pp + P.y) * pp + P.x);
 #pragma unroll
-        for (int j = 0; j < M2L_PER_WAVE; ++j) {
-            const int r = wave + 4 * j;
-            const int k = r % NC, bp = bp0 + r / NC;
-            reg[j] = Mb[(k * 8 + bp) * pp3 + poff];
+        for (int j = 0; j < M2L_ROWS_PER_THREAD; ++j) {
+            const int r = b + 8 * j;
+            int off = ((r % NC) * 8 + r / NC) * pp3;
+            asm volatile("" : "+s"(off));       // recomputed per tile: hoisted, five would pin registers
+            reg[j] = src[off];
         }
     };
     auto stash = [&](int buf, const double *reg) {
+        double *t = reinterpret_cast<double *>(&tile[buf][0][0][0]);
 #pragma unroll
-        for (int j = 0; j < M2L_PER_WAVE; ++j) tile[buf][wave + 4 * j][lane] = reg[j];
+        for (int j = 0; j < M2L_ROWS_PER_THREAD; ++j) {
+            const int r = b + 8 * j, i = r / NC, k = r % NC;
+            t[((i * (NC / 2) + (k >> 1)) * 64 + lane) * 2 + (k & 1)] = reg[j];
+        }
     };
 
-    double C0[NC], C1[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) { C0[k] = 0.0; C1[k] = 0.0; }
+    // compute cursor
+    int cb = fb, ci = fi, ct = 0;
+    int piece = d.piece0;
 
-    double reg[M2L_PER_WAVE];
-    fetch(0, reg);
+    double C[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) C[k] = 0.0;
+    auto flush = [&]() {
+        double *out = D.Cp + (size_t)piece * NC * 8 * np3 + lane_q(cb);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            out[(size_t)(k * 8 + b) * np3] = C[k];
+            C[k] = 0.0;
+        }
+    };
+
+    double reg[M2L_ROWS_PER_THREAD];
+    fetch(reg);
     stash(0, reg);
     __syncthreads();
 
-    for (int t = 0; t < ntiles; ++t) {
-        if (t + 1 < ntiles) fetch(t + 1, reg);
-        const int buf = t & 1;
-        const char4 P = plist[it.pbeg + t / (8 / M2L_TBP)];
-        const int bp0 = (t % (8 / M2L_TBP)) * M2L_TBP;
+    for (int k = 0; k < ntiles; ++k) {
+        if (k + 1 < ntiles) {
+            if (++ft == TPP) {
+                ft = 0;
+                if (++fi == nP) {
+                    fi = 0;
+                    fmq = lane_mq(++fb);
+                }
+            }
+            fetch(reg);
+        }
+        const int buf = k & 1;
+        const char4 P = plist[ci];
+        const int bp0 = ct * M2L_TBP;
 #pragma unroll
         for (int i = 0; i < M2L_TBP; ++i) {
             const int bp = bp0 + i;
-            const int sx = 2 * P.x + (bp & 1), sy = 2 * P.y + ((bp >> 1) & 1), sz = 2 * P.z + (bp >> 2);
-            double Ms[NC];
+            const int ox = 2 * P.x + (bp & 1) - (b & 1), oy = 2 * P.y + ((bp >> 1) & 1) - ((b >> 1) & 1),
+                      oz = 2 * P.z + (bp >> 2) - (b >> 2);
+            if (ox * ox + oy * oy + oz * oz <= r2i) continue;       // near: handled one level down
+            const double *Dr = Dl + off_index(ox, oy, oz) * NC;
+            double Dv[NC];
 #pragma unroll
-            for (int k = 0; k < NC; ++k) Ms[k] = tile[buf][i * NC + k][lane];
-            {
-                const int ox = sx - (b0 & 1), oy = sy - ((b0 >> 1) & 1), oz = sz - (b0 >> 2);
-                if (ox * ox + oy * oy + oz * oz > r2i) {
-                    const double *Dr = Dl + off_index(ox, oy, oz) * NC;
-                    double Dv[NC];
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) Dv[k] = Dr[k];
-                    m2l_apply(C0, Dv, Ms);
-                }
-            }
-            {
-                const int ox = sx - (b1 & 1), oy = sy - ((b1 >> 1) & 1), oz = sz - (b1 >> 2);
-                if (ox * ox + oy * oy + oz * oz > r2i) {
-                    const double *Dr = Dl + off_index(ox, oy, oz) * NC;
-                    double Dv[NC];
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) Dv[k] = Dr[k];
-                    m2l_apply(C1, Dv, Ms);
-                }
+            for (int q = 0; q < NC; ++q) Dv[q] = Dr[q];
+            m2l1_child(C, Dv, &tile[buf][i][0][0], lane, std::make_integer_sequence<int, NC / 2>{});
+        }
+        if (++ct == TPP) {
+            ct = 0;
+            if (++ci == nP) {                   // block complete: store its piece
+                flush();
+                piece = 0;
+                ci = 0;
+                ++cb;
             }
         }
-        if (t + 1 < ntiles) stash(buf ^ 1, reg);
+        if (k + 1 < ntiles) stash(buf ^ 1, reg);
         __syncthreads();
     }
-
-    const int64_t np = D.np;
-    const int64_t q = (qz * np + qy) * np + qx;
-    if (it.part < 0) {
-        const int64_t np3 = np * np * np;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            D.C[(k * 8 + b0) * np3 + q] = C0[k];
-            D.C[(k * 8 + b1) * np3 + q] = C1[k];
-        }
-    } else {
-        double *R = p.root_part + (size_t)it.part * NC * 8 * 64;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            R[(k * 8 + b0) * 64 + q] = C0[k];
-            R[(k * 8 + b1) * 64 + q] = C1[k];
-        }
-    }
+    if (ci != 0 || ct != 0) flush();            // run ended inside a block
 }
 
-// root local coefficients = sum of the partial sums of its work items
+// level 0: C = sum of the root's pieces
 __global__ __launch_bounds__(WG) void k_root_reduce(const DevPlan p)
 {
     const int t = blockIdx.x * WG + threadIdx.x;
     if (t >= NC * 8 * 64) return;
+    const DevLevel &D = p.lev[0];
     double s = 0.0;
-    for (int part = 0; part < p.n_root_parts; ++part) s += p.root_part[(size_t)part * NC * 8 * 64 + t];
-    p.lev[0].C[t] = s;
+    for (int piece = 0; piece < D.maxp; ++piece) s += D.Cp[(size_t)piece * NC * 8 * 64 + t];
+    D.C[t] = s;
 }
 
 // ------------------------------------------------------------------------
@@ -455,7 +570,11 @@ __global__ __launch_bounds__(WG) void k_l2l(const DevPlan p, int l)
     const int64_t q = (((int64_t)(cz >> 1)) * np + (cy >> 1)) * np + (cx >> 1);
     double Cc[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) Cc[k] = D.C[(k * 8 + bself) * np3 + q];
+    for (int k = 0; k < NC; ++k) {
+        double s = 0.0;
+        for (int piece = 0; piece < D.maxp; ++piece) s += D.Cp[((size_t)piece * NC * 8 + k * 8 + bself) * np3 + q];
+        Cc[k] = s;
+    }
     l2l_apply(Cc, e, Cp);
 #pragma unroll
     for (int k = 0; k < NC; ++k) D.C[(k * 8 + bself) * np3 + q] = Cc[k];
@@ -615,15 +734,20 @@ hipError_t launch_m2m(const DevPlan &p, int l, hipStream_t s)
 
 hipError_t launch_m2l(const DevPlan &p, hipStream_t s)
 {
-    if (p.n_items == 0) return hipSuccess;
-    const unsigned grid = (unsigned)(((p.n_items + 7) / 8) * 8);     // whole rounds over the 8 XCDs
-    hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(WG), 0, s, p);
+    if (p.n_mdesc == 0) return hipSuccess;
+    const unsigned grid = (unsigned)(((p.n_mdesc + 7) / 8) * 8);     // whole rounds over the 8 XCDs
+    hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(M2L_WG), 0, s, p, p.Dtab, p.plist_near, p.plist_cube, p.mdesc);
     return hipGetLastError();
+}
+
+hipError_t m2l_blocks_per_cu(int *n)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_m2l, M2L_WG, 0);
 }
 
 hipError_t launch_root_reduce(const DevPlan &p, hipStream_t s)
 {
-    if (p.n_root_parts == 0) return hipSuccess;
+    if (p.L < 1) return hipSuccess;
     hipLaunchKernelGGL(k_root_reduce, dim3(grid_for(NC * 8 * 64)), dim3(WG), 0, s, p);
     return hipGetLastError();
 }
