@@ -230,6 +230,45 @@ void build_tables(ot_fmm_plan P)
                 P->Kst[(i * 27 + e) * 4 + j] = P->Ktab[(size_t)off_index(ox, oy, oz) * 4 + j];
         }
 
+    // the adjoint leaf pass streams one source plane at a time: rows of K0,
+    // then of -K1x, -K1y, -K1z (the transpose flips the sign of the odd part)
+    const size_t nP = pl.size();
+    P->Ksa.assign(4 * nP * 27, 0.0);
+    for (int j = 0; j < 4; ++j)
+        for (size_t i = 0; i < nP; ++i)
+            for (int e = 0; e < 27; ++e)
+                P->Ksa[((size_t)j * nP + i) * 27 + e] = (j == 0 ? 1.0 : -1.0) * P->Kst[(i * 27 + e) * 4 + j];
+
+    // tree passes over the levels 0..L-2 in spans of at most three levels,
+    // aligned to the bottom: [L-4, L-2], [L-7, L-5], ... and a shorter top span
+    P->dp.n_span = 0;
+    {
+        int top = L - 1, spans[MAX_LEVELS][2], n = 0;
+        while (top > 0) {
+            const int lo = std::max(0, top - 3);
+            spans[n][0] = lo;
+            spans[n][1] = top - lo;
+            ++n;
+            top = lo;
+        }
+        for (int i = 0; i < n; ++i) {        // top-down order
+            P->dp.span_top[i] = spans[n - 1 - i][0];
+            P->dp.span_n[i] = spans[n - 1 - i][1];
+        }
+        P->dp.n_span = n;
+    }
+
+    // shift magnitudes e_a(x, x, x) of the leaf L2P (x = h/2); the sign of a
+    // component follows the child's octant
+    auto mags = [](double x, double *e) {
+        const double x2 = 0.5 * x * x;
+        const double v[NC] = {1.0, x, x, x, x2, x * x, x * x, x2, x * x, x2,
+                              x2 * x / 3.0, x2 * x, x2 * x, x * x2, x * x * x, x * x2,
+                              x2 * x / 3.0, x2 * x, x * x2, x2 * x / 3.0};
+        for (int k = 0; k < NC; ++k) e[k] = v[k];
+    };
+    mags(0.5 * h, P->dp.e_leaf);
+
     // derivative tensors per level l < L at R = z_sink - z_source = -o h_l
     const int nlev = std::max(L, 1);
     P->Dtab.assign((size_t)nlev * OFF_N * NC, 0.0);
@@ -427,6 +466,7 @@ int setup_device(ot_fmm_plan P)
     if ((rc = dev_upload(P, &d.leaf_slot, P->leaf_slot))) return rc;
     if ((rc = dev_upload(P, &d.Ktab, P->Ktab))) return rc;
     if ((rc = dev_upload(P, &d.Kst, P->Kst))) return rc;
+    if ((rc = dev_upload(P, &d.Ksa, P->Ksa))) return rc;
     if ((rc = dev_upload(P, &d.Dtab, P->Dtab))) return rc;
     if ((rc = dev_upload(P, &d.plist_near, P->plist_near))) return rc;
     if ((rc = dev_upload(P, &d.plist_cube, P->plist_cube))) return rc;
@@ -456,7 +496,7 @@ int setup_device(ot_fmm_plan P)
         v.nby = v.np / v.by;
         const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;
         if ((rc = dev_alloc(P, &v.M, (size_t)NC * 8 * pp3, true))) return rc;
-        if ((rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
+        if (l < L - 1 && (rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }
@@ -505,6 +545,32 @@ struct DeviceGuard {
         if (switched) (void)hipSetDevice(prev);
     }
 };
+
+// M2M over the levels L-2..0, the M2L of every level, and the L2L down to
+// level L-2; the forward and the adjoint share them (the leaf stages differ)
+hipError_t tree_passes(ot_fmm_plan P, hipStream_t s)
+{
+    const DevPlan &d = P->dp;
+    hipError_t e = hipSuccess;
+    if (d.n_span > 0) {
+        Phase ph(P, s, OT_FMM_PHASE_M2M, d.n_span);
+        for (int i = d.n_span - 1; i >= 0; --i)
+            if ((e = launch_m2m_span(d, i, s)) != hipSuccess) return e;
+        ph.end();
+    }
+    if (P->L >= 1) {
+        Phase ph(P, s, OT_FMM_PHASE_M2L, 1);
+        if ((e = launch_m2l(d, s)) != hipSuccess) return e;
+        ph.end();
+    }
+    if (d.n_span > 0) {
+        Phase ph(P, s, OT_FMM_PHASE_L2L, d.n_span);
+        for (int i = 0; i < d.n_span; ++i)
+            if ((e = launch_l2l_span(d, i, s)) != hipSuccess) return e;
+        ph.end();
+    }
+    return e;
+}
 
 }  // namespace
 
@@ -607,24 +673,7 @@ int ot_fmm_forward(ot_fmm_plan P, const double *rho, double *phi, double *g, voi
         if ((e = launch_upward_leaf(d, rho, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf");
         ph.end();
     }
-    if (P->L >= 2) {
-        Phase ph(P, s, OT_FMM_PHASE_M2M, P->L - 1);
-        for (int l = P->L - 2; l >= 0; --l)
-            if ((e = launch_m2m(d, l, s)) != hipSuccess) return hip_fail(e, "launch m2m");
-        ph.end();
-    }
-    if (P->L >= 1) {
-        {
-            Phase ph(P, s, OT_FMM_PHASE_M2L, 1);
-            if ((e = launch_m2l(d, s)) != hipSuccess) return hip_fail(e, "launch m2l");
-            ph.end();
-        }
-        Phase ph(P, s, OT_FMM_PHASE_L2L, P->L);
-        if ((e = launch_root_reduce(d, s)) != hipSuccess) return hip_fail(e, "launch root_reduce");
-        for (int l = 1; l < P->L; ++l)
-            if ((e = launch_l2l(d, l, s)) != hipSuccess) return hip_fail(e, "launch l2l");
-        ph.end();
-    }
+    if ((e = tree_passes(P, s)) != hipSuccess) return hip_fail(e, "launch of a tree pass");
     {
         Phase ph(P, s, OT_FMM_PHASE_LEAF, 1);
         if ((e = launch_leaf(d, phi, g, s)) != hipSuccess) return hip_fail(e, "launch leaf");
@@ -652,24 +701,7 @@ int ot_fmm_adjoint(ot_fmm_plan P, const double *dphi, const double *dg, double *
         if ((e = launch_upward_leaf_adj(d, dphi, dg, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf_adj");
         ph.end();
     }
-    if (P->L >= 2) {
-        Phase ph(P, s, OT_FMM_PHASE_M2M, P->L - 1);
-        for (int l = P->L - 2; l >= 0; --l)
-            if ((e = launch_m2m(d, l, s)) != hipSuccess) return hip_fail(e, "launch m2m");
-        ph.end();
-    }
-    if (P->L >= 1) {
-        {
-            Phase ph(P, s, OT_FMM_PHASE_M2L, 1);
-            if ((e = launch_m2l(d, s)) != hipSuccess) return hip_fail(e, "launch m2l");
-            ph.end();
-        }
-        Phase ph(P, s, OT_FMM_PHASE_L2L, P->L);
-        if ((e = launch_root_reduce(d, s)) != hipSuccess) return hip_fail(e, "launch root_reduce");
-        for (int l = 1; l < P->L; ++l)
-            if ((e = launch_l2l(d, l, s)) != hipSuccess) return hip_fail(e, "launch l2l");
-        ph.end();
-    }
+    if ((e = tree_passes(P, s)) != hipSuccess) return hip_fail(e, "launch of a tree pass");
     {
         Phase ph(P, s, OT_FMM_PHASE_LEAF_ADJ, 1);
         if ((e = launch_leaf_adj(d, drho, s)) != hipSuccess) return hip_fail(e, "launch leaf_adj");

@@ -6,7 +6,8 @@
 //   the leaves keeps
 //     M[l] : scaled moments   [NC][8][pp^3]  over the parent grid padded by a
 //            zero halo of hp parents per side (pp = np + 2 hp, np = n_l / 2),
-//     C[l] : local coefficients [NC][8][np^3],
+//     C[l] : local coefficients [NC][8][np^3]  (levels below L-1; the leaf
+//            pass forms the locals of level L-1 in registers),
 //   so the 64 lanes of a wave that handle 64 neighbouring parents read
 //   consecutive addresses, and the stencil never needs a bounds check.
 //   The leaf sources (masses, or the adjoint's cotangents) are staged in the
@@ -45,7 +46,7 @@ struct DevLevel {
     int nbx, nby;    // blocks per axis in x and y
     double h;        // cell width of this level
     double *M;       // [NC][8][pp^3]
-    double *C;       // [NC][8][np^3] local coefficients (final)
+    double *C;       // [NC][8][np^3] local coefficients (final); null at level L-1
     double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
 };
 
@@ -75,11 +76,15 @@ struct DevPlan {
     double *src;                // [4][8][ppL^3]
     const double *Ktab;         // [OFF_N][4]: K0, K1x, K1y, K1z of a leaf pair
     const double *Kst;          // [n_plist_leaf][27][4]: Ktab rows of 2P + e, e in {-1,0,1}^3
+    const double *Ksa;          // [4][n_plist_leaf][27]: the same rows plane by plane for the
+                                //   adjoint leaf pass: K0, then -K1x, -K1y, -K1z
     const double *Dtab;         // [L][OFF_N][NC]: derivative tensor of -G/r per level
     const char4 *plist_leaf; int n_plist_leaf;   // parent offsets of the leaf P2P
     const char4 *plist_near; int n_plist_near;   // |P| <= 1/theta (levels >= 1)
     const char4 *plist_cube; int n_plist_cube;   // [-3,3]^3 (root level)
     const M2LDesc *mdesc; int n_mdesc;          // one per M2L workgroup
+    int n_span; int span_top[MAX_LEVELS], span_n[MAX_LEVELS];   // tree passes over levels 0..L-2
+    double e_leaf[NC];   // e_a(h/2, h/2, h/2): L2P shift magnitudes, leaf cell from its parent
     DevLevel lev[MAX_LEVELS];
 };
 
@@ -110,7 +115,7 @@ struct ot_fmm_plan_s {
     std::vector<int32_t> leaf_slot;
     std::vector<char4> plist_near, plist_cube;
     std::vector<otfmm::M2LDesc> mdesc;
-    std::vector<double> Ktab, Kst, Dtab;
+    std::vector<double> Ktab, Kst, Ksa, Dtab;
     ot_fmm_info info{};
 
     // device state
@@ -124,11 +129,10 @@ namespace otfmm {
 // kernel launchers (ot_fmm_kernels.hip); each returns hipGetLastError()
 hipError_t launch_upward_leaf(const DevPlan &p, const double *rho, hipStream_t s);
 hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const double *u, hipStream_t s);
-hipError_t launch_m2m(const DevPlan &p, int level, hipStream_t s);
+hipError_t launch_m2m_span(const DevPlan &p, int span, hipStream_t s);
 hipError_t launch_m2l(const DevPlan &p, hipStream_t s);
-hipError_t launch_root_reduce(const DevPlan &p, hipStream_t s);
 hipError_t m2l_blocks_per_cu(int *n);   // resident M2L workgroups per CU
-hipError_t launch_l2l(const DevPlan &p, int level, hipStream_t s);
+hipError_t launch_l2l_span(const DevPlan &p, int span, hipStream_t s);
 hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s);
 hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s);
 

@@ -133,19 +133,7 @@ constexpr int source_begin(int b)
 }
 static_assert(source_begin(NC) == 84, "source-major term ranges");
 
-// Two sinks share each source component m = M[b]:
-//   C0[a] += D0[a+b] m,  C1[a] += D1[a+b] m  for the terms of component b
-template <int B, int... I>
-__device__ __forceinline__ void m2l2_component(double *C0, double *C1, const double *D0, const double *D1,
-                                               double m, std::integer_sequence<int, I...>)
-{
-    constexpr Terms<84> T = make_sum_terms_by_source();
-    constexpr int o = source_begin(B);
-    ((C0[T.t[o + I].i] = fma(D0[T.t[o + I].k], m, C0[T.t[o + I].i]),
-      C1[T.t[o + I].i] = fma(D1[T.t[o + I].k], m, C1[T.t[o + I].i])), ...);
-}
-
-// one sink only
+// one sink:  C[a] += D[a+b] m  for the terms of source component b
 template <int B, int... I>
 __device__ __forceinline__ void m2l1_component(double *C, const double *D, double m, std::integer_sequence<int, I...>)
 {
@@ -157,19 +145,6 @@ __device__ __forceinline__ void m2l1_component(double *C, const double *D, doubl
 constexpr int terms_of_source(int b)
 {
     return (order_of(b) == 0) ? 20 : (order_of(b) == 1) ? 10 : (order_of(b) == 2) ? 4 : 1;
-}
-
-// C[a] += D[a+b] M[b] over all 84 terms
-template <int... I>
-__device__ __forceinline__ void m2l_terms(double *C, const double *D, const double *M,
-                                          std::integer_sequence<int, I...>)
-{
-    constexpr Terms<84> T = make_sum_terms();
-    ((C[T.t[I].i] = fma(D[T.t[I].k], M[T.t[I].j], C[T.t[I].i])), ...);
-}
-__device__ __forceinline__ void m2l_apply(double *C, const double *D, const double *M)
-{
-    m2l_terms(C, D, M, std::make_integer_sequence<int, 84>{});
 }
 
 // Cc[a] += e[g] Cp[a+g]
@@ -211,19 +186,6 @@ __device__ __forceinline__ void dipole_apply(double *Mp, const double *e, const 
     dipole_terms(Mp, e, u, std::make_integer_sequence<int, 30>{});
 }
 
-// grad[k] += e[g] C[g + e_k]
-template <int... I>
-__device__ __forceinline__ void grad_terms(double *grad, const double *e, const double *C,
-                                           std::integer_sequence<int, I...>)
-{
-    constexpr Terms<30> T = make_grad_terms();
-    ((grad[T.t[I].i] = fma(e[T.t[I].j], C[T.t[I].k], grad[T.t[I].i])), ...);
-}
-__device__ __forceinline__ void grad_apply(double *grad, const double *e, const double *C)
-{
-    grad_terms(grad, e, C, std::make_integer_sequence<int, 30>{});
-}
-
 // e_a(x) = x^a / a!
 __device__ __forceinline__ void taylor(double x, double y, double z, double *e)
 {
@@ -236,6 +198,16 @@ __device__ __forceinline__ void taylor(double x, double y, double z, double *e)
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
+// renumbering them this way gives each XCD a contiguous run of work items,
+// so neighbouring items that share data share an L2.  The grid is a
+// multiple of 8.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks)
+{
+    const int per = (nblocks + 7) >> 3;          // items per XCD
+    return (bid & 7) * per + (bid >> 3);
+}
 
 // 64 lanes of a wave cover a block of bx*by*bz parents of an np^3 grid
 struct Block { int bx, by, bz; };
@@ -303,77 +275,111 @@ __global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const doubl
     }
 }
 
-// ------------------------------------------------------------------------
-// M2M into level l from level l+1: lane = one cell c of level l
-// ------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_m2m(const DevPlan p, int l)
+typedef __attribute__((address_space(1))) double gdouble;   // global memory
+
+// C[k] += sum over the pieces of cp[(piece * NC + k) * cs]; all loads of a
+// piece are issued before the first add
+__device__ __forceinline__ void add_pieces(double *C, const double *cp, int64_t cs, int maxp)
 {
-    const DevLevel &D = p.lev[l];
-    const DevLevel &Dc = p.lev[l + 1];
-    const int n = 2 * D.np;
-    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (t >= (int64_t)n * n * n) return;
-    const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
-    const int64_t ppc3 = (int64_t)Dc.pp * Dc.pp * Dc.pp;
-    const int64_t padc = ((int64_t)(cz + Dc.hp) * Dc.pp + (cy + Dc.hp)) * Dc.pp + (cx + Dc.hp);
-    const double hh = 0.5 * Dc.h;
-    double Mp[NC];
+    for (int piece = 0; piece < maxp; ++piece) {
+        const double *pc = cp + piece * NC * cs;
+        asm volatile("" : "+v"(pc));     // one address per piece, not one induction pointer per component
+        const gdouble *g = (const gdouble *)pc;
+        double t[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) Mp[k] = 0.0;
-#pragma unroll 1
-    for (int b = 0; b < 8; ++b) {
-        double Mc[NC], e[NC];
+        for (int k = 0; k < NC; ++k) t[k] = g[k * cs];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) Mc[k] = Dc.M[(k * 8 + b) * ppc3 + padc];
-        taylor((b & 1) ? -hh : hh, ((b >> 1) & 1) ? -hh : hh, (b >> 2) ? -hh : hh, e);
-        m2m_apply(Mp, e, Mc);
+        for (int k = 0; k < NC; ++k) C[k] += t[k];
     }
-    const int bself = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
-    const int64_t pp3 = (int64_t)D.pp * D.pp * D.pp;
-    const int64_t padq = ((int64_t)((cz >> 1) + D.hp) * D.pp + ((cy >> 1) + D.hp)) * D.pp + ((cx >> 1) + D.hp);
-#pragma unroll
-    for (int k = 0; k < NC; ++k) D.M[(k * 8 + bself) * pp3 + padq] = Mp[k];
 }
 
 // ------------------------------------------------------------------------
-// M2L, every level below the leaves in one launch.
-//
-// Workgroup = one work item: 64 sink parents of one level (lane = parent)
-// and a range of parent offsets P; wave w handles the sink children
-// b = 2w and 2w+1.  All four waves need the same source moments (the
-// children of q + P), so the source tile of two source children (2 x 20
-// components x 64 parents, 20 KB) is loaded once per workgroup -- each wave
-// fetches a quarter of the components of its lane's own source parent --
-// and shared through LDS, double-buffered: the next tile is loaded into
-// registers while the current one is consumed.
-//
-// Items are assigned so that each XCD walks a contiguous run of them
-// (workgroups are dealt round-robin to the 8 XCDs), which keeps the
-// neighbouring blocks that share source halos on one L2.
+// Tree passes over a span of levels [t, t + n), n <= 3, in one launch: a
+// workgroup owns one cell A of level t and its descendants down to level
+// t + n - 1 (1 + 8 + 64 cells).  The cells of the span at depth j are
+// numbered by their path from A, three bits (the child index) per level.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void span_cell(int ax, int ay, int az, int j, int idx, int &cx, int &cy, int &cz)
+{
+    cx = ax; cy = ay; cz = az;
+    for (int i = j - 1; i >= 0; --i) {
+        const int b = (idx >> (3 * i)) & 7;
+        cx = 2 * cx + (b & 1);
+        cy = 2 * cy + ((b >> 1) & 1);
+        cz = 2 * cz + (b >> 2);
+    }
+}
+
+// M2M, deepest level of the span first.  Thread t = (cell ci, child b) of a
+// step shifts the moments of child b to the centre of cell ci; the 8
+// children of a cell sit in 8 consecutive lanes and are summed by shuffles
+// in a fixed order.  Children of the deepest cells come from memory, the
+// others from the previous step through LDS.
+constexpr int M2M_SPAN_WG = 512;
+
+__global__ __launch_bounds__(M2M_SPAN_WG) void k_m2m_span(const DevPlan p, int ltop, int nlev)
+{
+    __shared__ double Ms[2][64][NC];      // moments of the span's cells at depths 1 and 2
+    const int n = 8 << ltop;
+    const int a = xcd_remap(blockIdx.x, gridDim.x);
+    if (a >= n * n * n) return;
+    const int ax = a % n, ay = (a / n) % n, az = a / (n * n);
+    const int t = threadIdx.x;
+    const int b = t & 7, ci = t >> 3;
+    for (int j = nlev - 1; j >= 0; --j) {
+        const int lv = ltop + j;
+        const bool act = ci < (1 << (3 * j));
+        int cx, cy, cz;
+        span_cell(ax, ay, az, j, ci, cx, cy, cz);
+        double Mc[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Mc[k] = 0.0;
+        if (act) {
+            if (j == nlev - 1) {
+                // the children of c are stored under c in level lv + 1
+                const DevLevel &Dc = p.lev[lv + 1];
+                const int64_t pp = Dc.pp, pp3 = pp * pp * pp;
+                const int64_t pad = ((int64_t)(cz + Dc.hp) * pp + (cy + Dc.hp)) * pp + (cx + Dc.hp);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Mc[k] = Dc.M[(k * 8 + b) * pp3 + pad];
+            } else {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Mc[k] = Ms[(j + 1) & 1][ci * 8 + b][k];
+            }
+        }
+        const double hh = 0.5 * p.lev[lv + 1].h;
+        double e[NC], Mp[NC];
+        taylor((b & 1) ? -hh : hh, ((b >> 1) & 1) ? -hh : hh, (b >> 2) ? -hh : hh, e);   // e(z_c - z_child)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Mp[k] = 0.0;
+        m2m_apply(Mp, e, Mc);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            Mp[k] += __shfl_down(Mp[k], 4, 8);
+            Mp[k] += __shfl_down(Mp[k], 2, 8);
+            Mp[k] += __shfl_down(Mp[k], 1, 8);
+        }
+        if (act && b == 0) {
+            if (j > 0) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Ms[j & 1][ci][k] = Mp[k];
+            }
+            const DevLevel &D = p.lev[lv];
+            const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+            const int64_t pp = D.pp, pp3 = pp * pp * pp;
+            const int64_t pad = ((int64_t)((cz >> 1) + D.hp) * pp + ((cy >> 1) + D.hp)) * pp + ((cx >> 1) + D.hp);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) D.M[(k * 8 + bs) * pp3 + pad] = Mp[k];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// M2L
 // ------------------------------------------------------------------------
 constexpr int M2L_TBP = 2;                       // source children per tile
 constexpr int M2L_TILE = M2L_TBP * NC;           // (child, component) rows per tile
-
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks)
-{
-    const int per = (nblocks + 7) >> 3;          // items per XCD
-    return (bid & 7) * per + (bid >> 3);
-}
-
-// row[b * 64]: component b of this lane's source in the LDS tile
-template <int... B>
-__device__ __forceinline__ void m2l2_source(double *C0, double *C1, const double *D0, const double *D1,
-                                            const double *row, std::integer_sequence<int, B...>)
-{
-    (m2l2_component<B>(C0, C1, D0, D1, row[B * 64], std::make_integer_sequence<int, terms_of_source(B)>{}), ...);
-}
-
-template <int... B>
-__device__ __forceinline__ void m2l1_source(double *C, const double *D, const double *row,
-                                            std::integer_sequence<int, B...>)
-{
-    (m2l1_component<B>(C, D, row[B * 64], std::make_integer_sequence<int, terms_of_source(B)>{}), ...);
-}
 
 // M2L over every level below the leaves in one launch.
 //
@@ -531,66 +537,174 @@ __global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *_
     if (ci != 0 || ct != 0) flush();            // run ended inside a block
 }
 
-// level 0: C = sum of the root's pieces
-__global__ __launch_bounds__(WG) void k_root_reduce(const DevPlan p)
-{
-    const int t = blockIdx.x * WG + threadIdx.x;
-    if (t >= NC * 8 * 64) return;
-    const DevLevel &D = p.lev[0];
-    double s = 0.0;
-    for (int piece = 0; piece < D.maxp; ++piece) s += D.Cp[(size_t)piece * NC * 8 * 64 + t];
-    D.C[t] = s;
-}
+// L2L over a span, top level first.  Thread groups: t = 0 the cell A,
+// t in [1, 9) its children, t in [9, 73) its grandchildren.  Every thread
+// first adds the M2L pieces of its cell (they do not depend on the parents),
+// then, level by level, the shift of its parent's final expansion (from
+// memory for A, from LDS below it).
+constexpr int L2L_SPAN_WG = 128;
 
-// ------------------------------------------------------------------------
-// L2L into level l >= 1 from level l-1: lane = one cell c of level l
-// ------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_l2l(const DevPlan p, int l)
+__global__ __launch_bounds__(L2L_SPAN_WG) void k_l2l_span(const DevPlan p, int ltop, int nlev)
 {
-    const DevLevel &D = p.lev[l];
-    const DevLevel &Dp = p.lev[l - 1];
-    const int n = 2 * D.np;
-    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (t >= (int64_t)n * n * n) return;
-    const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
-    // parent cell P = c >> 1 of level l-1, stored under its own parent P >> 1
-    const int Px = cx >> 1, Py = cy >> 1, Pz = cz >> 1;
-    const int bP = (Px & 1) + 2 * (Py & 1) + 4 * (Pz & 1);
-    const int64_t npp = Dp.np;
-    const int64_t qP = (((int64_t)(Pz >> 1)) * npp + (Py >> 1)) * npp + (Px >> 1);
-    const int64_t npp3 = npp * npp * npp;
-    double Cp[NC], e[NC];
+    __shared__ double Cs0[NC], Cs1[8][NC];
+    const int n = 8 << ltop;
+    const int a = xcd_remap(blockIdx.x, gridDim.x);
+    if (a >= n * n * n) return;
+    const int ax = a % n, ay = (a / n) % n, az = a / (n * n);
+    const int t = threadIdx.x;
+    const int j = (t == 0) ? 0 : (t < 9 ? 1 : 2);
+    const int ci = (t == 0) ? 0 : (t < 9 ? t - 1 : t - 9);
+    const bool act = t < 73 && j < nlev;
+    const int lv = ltop + j;
+    int cx, cy, cz;
+    span_cell(ax, ay, az, j, ci, cx, cy, cz);
+    const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+    double C[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) Cp[k] = Dp.C[(k * 8 + bP) * npp3 + qP];
-    const double hh = 0.5 * D.h;
-    taylor((cx & 1) ? hh : -hh, (cy & 1) ? hh : -hh, (cz & 1) ? hh : -hh, e);   // e(z_c - z_P)
-    const int bself = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
-    const int64_t np = D.np;
-    const int64_t np3 = np * np * np;
-    const int64_t q = (((int64_t)(cz >> 1)) * np + (cy >> 1)) * np + (cx >> 1);
-    double Cc[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        double s = 0.0;
-        for (int piece = 0; piece < D.maxp; ++piece) s += D.Cp[((size_t)piece * NC * 8 + k * 8 + bself) * np3 + q];
-        Cc[k] = s;
+    for (int k = 0; k < NC; ++k) C[k] = 0.0;
+    int64_t np3 = 0, q = 0;
+    if (act) {
+        const DevLevel &D = p.lev[lv];
+        const int64_t np = D.np;
+        np3 = np * np * np;
+        q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
+        add_pieces(C, D.Cp + bs * np3 + q, 8 * np3, D.maxp);
     }
-    l2l_apply(Cc, e, Cp);
+    for (int st = 0; st < nlev; ++st) {
+        if (act && j == st) {
+            double Cp[NC];
+            bool shift = true;
+            if (st == 0) {
+                if (ltop > 0) {          // parent R = c >> 1 of level ltop - 1, final
+                    const DevLevel &Dp = p.lev[ltop - 1];
+                    const int Rx = cx >> 1, Ry = cy >> 1, Rz = cz >> 1;
+                    const int bR = (Rx & 1) + 2 * (Ry & 1) + 4 * (Rz & 1);
+                    const int64_t npp = Dp.np, npp3 = npp * npp * npp;
+                    const int64_t qR = ((int64_t)(Rz >> 1) * npp + (Ry >> 1)) * npp + (Rx >> 1);
 #pragma unroll
-    for (int k = 0; k < NC; ++k) D.C[(k * 8 + bself) * np3 + q] = Cc[k];
+                    for (int k = 0; k < NC; ++k) Cp[k] = Dp.C[(k * 8 + bR) * npp3 + qR];
+                } else {
+                    shift = false;
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) Cp[k] = 0.0;
+                }
+            } else if (st == 1) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Cp[k] = Cs0[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Cp[k] = Cs1[ci >> 3][k];
+            }
+            if (shift) {
+                const double hh = 0.5 * p.lev[lv].h;
+                double e[NC];
+                taylor((cx & 1) ? hh : -hh, (cy & 1) ? hh : -hh, (cz & 1) ? hh : -hh, e);   // e(z_c - z_parent)
+                l2l_apply(C, e, Cp);
+            }
+            if (st == 0 && nlev > 1) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Cs0[k] = C[k];
+            } else if (st == 1 && nlev > 2) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Cs1[ci][k] = C[k];
+            }
+            double *out = p.lev[lv].C;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) out[(k * 8 + bs) * np3 + q] = C[k];
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------------
-// Leaf pass: P2P over the leaf stencil + L2L/L2P from level L-1.
-// A wave owns 64 leaf parents Q (lane = Q) and all 8 children of each.  For
-// a parent offset P the 64 child pairs (b', b) use the 27 offsets
-// 2P + e, e = b' - b in {-1,0,1}^3; Kst holds, per entry of the parent-offset
-// list, those 27 rows of (K0, K1x, K1y, K1z), so each row is one scalar load
-// at a constant offset and serves every pair with that e.  The sources of the
-// next P are loaded while the current ones are consumed.
+// Leaf pass: local expansion of the leaf parent, L2P, then P2P over the
+// leaf stencil.
+//
+// A wave owns 64 leaf parents Q (lane = Q) and all 8 children of each.
+// The local expansion of Q (level L-1) is its M2L pieces plus the shift of
+// its parent's, formed in registers; it is evaluated at the 8 children
+// first, so it is dead before the pair loop starts.  For a parent offset P
+// the 64 child pairs (b', b) use the 27 offsets 2P + e, e = b' - b in
+// {-1,0,1}^3; the stream tables hold, per step, those 27 kernel rows, read
+// through scalar loads, each serving every pair with that e.  The forward
+// pass takes one source plane (the mass) and four accumulators per child;
+// the adjoint takes four planes (w, u) and one accumulator, and runs the
+// planes one after the other, so the sources in flight at a time are a
+// single plane, whose neighbourhood stays in L2.  The sources of the next
+// step are loaded while the current ones are consumed.
 // ------------------------------------------------------------------------
+
+// octant sign of e_a at child b: along an axis whose bit is 0 the child
+// centre lies at -x from its parent
+constexpr bool neg_of(int b, int a)
+{
+    return ((kMI[a].t * (1 - (b & 1)) + kMI[a].u * (1 - ((b >> 1) & 1)) + kMI[a].v * (1 - (b >> 2))) & 1) != 0;
+}
+
+// potential of the local expansion C at child B: sum_a e_a C[a]
+template <int B, int... A>
+__device__ __forceinline__ double l2p_phi(const double *C, const double *em, std::integer_sequence<int, A...>)
+{
+    double s = 0.0;
+    ((s = fma(neg_of(B, A) ? -em[A] : em[A], C[A], s)), ...);
+    return s;
+}
+
+// gradient at child B: gr[k] += e_g C[g + e_k], |g| <= 2
+template <int B, int... I>
+__device__ __forceinline__ void l2p_grad(double *gr, const double *C, const double *em, std::integer_sequence<int, I...>)
+{
+    constexpr Terms<30> T = make_grad_terms();
+    ((gr[T.t[I].i] = fma(neg_of(B, T.t[I].j) ? -em[T.t[I].j] : em[T.t[I].j], C[T.t[I].k], gr[T.t[I].i])), ...);
+}
+
+template <bool ADJ, int NA, int... B>
+__device__ __forceinline__ void leaf_l2p(double (&acc)[8][NA], const double *C, const double *em,
+                                         std::integer_sequence<int, B...>)
+{
+    ((acc[B][0] = l2p_phi<B>(C, em, std::make_integer_sequence<int, NC>{})), ...);
+    if constexpr (!ADJ) {
+        auto grad = [&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            double gr[3] = {0.0, 0.0, 0.0};
+            l2p_grad<b>(gr, C, em, std::make_integer_sequence<int, 30>{});
+            acc[b][1 % NA] = -gr[0];
+            acc[b][2 % NA] = -gr[1];
+            acc[b][3 % NA] = -gr[2];
+        };
+        (grad(std::integral_constant<int, B>{}), ...);
+    }
+}
+
+// local expansion of leaf parent Q (a cell of level L-1): its M2L pieces
+// plus the L2L shift of its parent's final expansion (level L-2)
+__device__ __forceinline__ void leaf_parent_local(const DevPlan &p, int Qx, int Qy, int Qz, double *C)
+{
+#pragma unroll
+    for (int k = 0; k < NC; ++k) C[k] = 0.0;
+    if (p.L < 1) return;
+    const DevLevel &D = p.lev[p.L - 1];
+    const int bQ = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
+    const int64_t nq = D.np, nq3 = nq * nq * nq;
+    const int64_t q = ((int64_t)(Qz >> 1) * nq + (Qy >> 1)) * nq + (Qx >> 1);
+    add_pieces(C, D.Cp + bQ * nq3 + q, 8 * nq3, D.maxp);
+    if (p.L < 2) return;
+    const DevLevel &Dp = p.lev[p.L - 2];
+    const int Rx = Qx >> 1, Ry = Qy >> 1, Rz = Qz >> 1;
+    const int bR = (Rx & 1) + 2 * (Ry & 1) + 4 * (Rz & 1);
+    const int64_t nr = Dp.np, nr3 = nr * nr * nr;
+    const int64_t r = ((int64_t)(Rz >> 1) * nr + (Ry >> 1)) * nr + (Rx >> 1);
+    double CR[NC], e[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) CR[k] = Dp.C[(k * 8 + bR) * nr3 + r];
+    const double hh = p.hleaf;                  // half the width of a leaf parent
+    taylor((Qx & 1) ? hh : -hh, (Qy & 1) ? hh : -hh, (Qz & 1) ? hh : -hh, e);   // e(z_Q - z_R)
+    l2l_apply(C, e, CR);
+}
+
 template <bool ADJ>
-__global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, double *__restrict__ out0,
+__global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__restrict__ Ks,
+                                             const char4 *__restrict__ plist, double *__restrict__ out0,
                                              double *__restrict__ out1)
 {
     const int npL = p.npL;
@@ -607,84 +721,112 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, double *__restrict
     const double *__restrict__ S = p.src + ((Qz + p.hpL) * pp + (Qy + p.hpL)) * pp + (Qx + p.hpL);
 
     constexpr int NA = ADJ ? 1 : 4;     // accumulators per sink child
-    constexpr int NS = ADJ ? 4 : 1;     // source planes
     double acc[8][NA];
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-#pragma unroll
-        for (int j = 0; j < NA; ++j) acc[b][j] = 0.0;
-
-    auto fetch = [&](int pi, double (*dst)[NS]) {
-        const char4 P = p.plist_leaf[pi];
-        const int64_t poff = ((int64_t)P.z * pp + P.y) * pp + P.x;
-#pragma unroll
-        for (int bp = 0; bp < 8; ++bp)
-#pragma unroll
-            for (int j = 0; j < NS; ++j) dst[bp][j] = S[(j * 8 + bp) * ppL3 + poff];
-    };
-
-    const int np = p.n_plist_leaf;
-    double cur[8][NS], nxt[8][NS];
-    fetch(0, cur);
-    for (int pi = 0; pi < np; ++pi) {
-        if (pi + 1 < np) fetch(pi + 1, nxt);
-        const double *__restrict__ Kp = p.Kst + (size_t)pi * 27 * 4;
-#pragma unroll
-        for (int e = 0; e < 27; ++e) {
-            const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
-            const double k0 = Kp[4 * e], k1 = Kp[4 * e + 1], k2 = Kp[4 * e + 2], k3 = Kp[4 * e + 3];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int bx = (b & 1) + ex, by = ((b >> 1) & 1) + ey, bz = (b >> 2) + ez;
-                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
-                const int bp = bx + 2 * by + 4 * bz;
-                if constexpr (!ADJ) {
-                    acc[b][0] = fma(k0, cur[bp][0], acc[b][0]);
-                    acc[b][1 % NA] = fma(k1, cur[bp][0], acc[b][1 % NA]);
-                    acc[b][2 % NA] = fma(k2, cur[bp][0], acc[b][2 % NA]);
-                    acc[b][3 % NA] = fma(k3, cur[bp][0], acc[b][3 % NA]);
-                } else {
-                    // transpose of the P2P: K0 even, K1 odd in the offset
-                    double a = fma(k0, cur[bp][0], acc[b][0]);
-                    a = fma(-k1, cur[bp][1 % NS], a);
-                    a = fma(-k2, cur[bp][2 % NS], a);
-                    acc[b][0] = fma(-k3, cur[bp][3 % NS], a);
-                }
-            }
-        }
-        if (pi + 1 < np) {
-#pragma unroll
-            for (int bp = 0; bp < 8; ++bp)
-#pragma unroll
-                for (int j = 0; j < NS; ++j) cur[bp][j] = nxt[bp][j];
-        }
+    {
+        double C[NC];
+        leaf_parent_local(p, Qx, Qy, Qz, C);
+        leaf_l2p<ADJ, NA>(acc, C, p.e_leaf, std::make_integer_sequence<int, 8>{});
     }
 
-    if (p.L >= 1) {
-        const DevLevel &D = p.lev[p.L - 1];
-        const int bQ = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
-        const int64_t nq = D.np;
-        const int64_t nq3 = nq * nq * nq;
-        const int64_t q = (((int64_t)(Qz >> 1)) * nq + (Qy >> 1)) * nq + (Qx >> 1);
-        double C[NC];
+    // The fetch of the next step is unconditional (the last step re-reads a
+    // valid entry): a conditional one would merge the wait counts of both
+    // paths and make every step wait for its own prefetch.  A scheduling
+    // barrier keeps the loads ahead of the step's arithmetic, and the
+    // prefetched values pass through an empty asm after it, so the compiler
+    // cannot fold the rotation into a load at the top of the loop.
+    const int nP = p.n_plist_leaf;
+    if constexpr (!ADJ) {
+        double cur[8], nxt[8];
+        auto fetch = [&](int pi, double *dst) {
+            const char4 P = plist[pi];
+            const double *src = S + ((int64_t)P.z * pp + P.y) * pp + P.x;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) C[k] = D.C[(k * 8 + bQ) * nq3 + q];
-        const double hh = 0.5 * p.hleaf;
+            for (int bp = 0; bp < 8; ++bp) dst[bp] = src[bp * ppL3];
+        };
+        fetch(0, cur);
+        for (int pi = 0; pi < nP; ++pi) {
+            fetch(pi + 1 < nP ? pi + 1 : pi, nxt);
+            __builtin_amdgcn_sched_barrier(0);      // keep the prefetch ahead of the arithmetic
+            const double *__restrict__ K = Ks + (size_t)pi * 27 * 4;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            double e[NC];
-            taylor((b & 1) ? hh : -hh, ((b >> 1) & 1) ? hh : -hh, (b >> 2) ? hh : -hh, e);  // e(z_leaf - z_Q)
-            double ph = 0.0;
+            for (int e = 0; e < 27; ++e) {
+                const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+                const double k0 = K[4 * e], k1 = K[4 * e + 1], k2 = K[4 * e + 2], k3 = K[4 * e + 3];
 #pragma unroll
-            for (int k = 0; k < NC; ++k) ph = fma(e[k], C[k], ph);
-            acc[b][0] += ph;
-            if constexpr (!ADJ) {
-                double gr[3] = {0.0, 0.0, 0.0};
-                grad_apply(gr, e, C);
-                acc[b][1 % NA] -= gr[0];
-                acc[b][2 % NA] -= gr[1];
-                acc[b][3 % NA] -= gr[2];
+                for (int b = 0; b < 8; ++b) {
+                    const int bx = (b & 1) + ex, by = ((b >> 1) & 1) + ey, bz = (b >> 2) + ez;
+                    if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                    const double m = cur[bx + 2 * by + 4 * bz];
+                    acc[b][0] = fma(k0, m, acc[b][0]);
+                    acc[b][1 % NA] = fma(k1, m, acc[b][1 % NA]);
+                    acc[b][2 % NA] = fma(k2, m, acc[b][2 % NA]);
+                    acc[b][3 % NA] = fma(k3, m, acc[b][3 % NA]);
+                }
             }
+#pragma unroll
+            for (int bp = 0; bp < 8; ++bp) {
+                asm("" : "+v"(nxt[bp]));
+                cur[bp] = nxt[bp];
+            }
+        }
+    } else {
+        // Steps run over (plane j, list entry i), plane-major, 27 rows of Ks
+        // each.  A step has a quarter of the forward's arithmetic, so the
+        // sources travel in a ring of four register sets, fetched three
+        // steps before use; the loop is unrolled by four (4 nP steps), so the
+        // ring needs no register copies.
+        auto fetch = [&](int j, int pi, double *dst) {
+            const char4 P = plist[pi];
+            const double *src = S + (int64_t)j * 8 * ppL3 + ((int64_t)P.z * pp + P.y) * pp + P.x;
+#pragma unroll
+            for (int bp = 0; bp < 8; ++bp) dst[bp] = src[bp * ppL3];
+        };
+        int fj = 0, fi = 0;              // plane and entry of the next fetch
+        auto fetch_next = [&](double *dst) {    // wraps to the start after the last step
+            fetch(fj, fi, dst);
+            if (++fi == nP) {
+                fi = 0;
+                fj = (fj == 3) ? 0 : fj + 1;
+            }
+        };
+        auto step = [&](int st, const double *src) {
+            const double *__restrict__ K = Ks + (size_t)st * 27;
+#pragma unroll
+            for (int e = 0; e < 27; ++e) {
+                const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+                const double k = K[e];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int bx = (b & 1) + ex, by = ((b >> 1) & 1) + ey, bz = (b >> 2) + ez;
+                    if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                    acc[b][0] = fma(k, src[bx + 2 * by + 4 * bz], acc[b][0]);
+                }
+            }
+        };
+        double r0[8], r1[8], r2[8], r3[8];
+        // issue order r0..r3 here as in the loop, so the wait counts agree
+        fetch_next(r0);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch_next(r1);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch_next(r2);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch_next(r3);
+        __builtin_amdgcn_sched_barrier(0);
+        for (int st = 0; st < 4 * nP; st += 4) {
+            step(st, r0);
+            fetch_next(r0);
+            __builtin_amdgcn_sched_barrier(0);
+            step(st + 1, r1);
+            fetch_next(r1);
+            __builtin_amdgcn_sched_barrier(0);
+            step(st + 2, r2);
+            fetch_next(r2);
+            __builtin_amdgcn_sched_barrier(0);
+            step(st + 3, r3);
+            fetch_next(r3);
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("" ::: "memory");      // no folding of the ring into loads at the loop head
         }
     }
 
@@ -725,10 +867,13 @@ hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_m2m(const DevPlan &p, int l, hipStream_t s)
+static inline unsigned grid_x8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
+
+hipError_t launch_m2m_span(const DevPlan &p, int i, hipStream_t s)
 {
-    const int64_t n = 2 * (int64_t)p.lev[l].np;
-    hipLaunchKernelGGL(k_m2m, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l);
+    const int t = p.span_top[i], nl = p.span_n[i];
+    const int64_t n = 8 << t;
+    hipLaunchKernelGGL(k_m2m_span, dim3(grid_x8(n * n * n)), dim3(nl == 3 ? M2M_SPAN_WG : 64), 0, s, p, t, nl);
     return hipGetLastError();
 }
 
@@ -745,17 +890,11 @@ hipError_t m2l_blocks_per_cu(int *n)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_m2l, M2L_WG, 0);
 }
 
-hipError_t launch_root_reduce(const DevPlan &p, hipStream_t s)
+hipError_t launch_l2l_span(const DevPlan &p, int i, hipStream_t s)
 {
-    if (p.L < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_root_reduce, dim3(grid_for(NC * 8 * 64)), dim3(WG), 0, s, p);
-    return hipGetLastError();
-}
-
-hipError_t launch_l2l(const DevPlan &p, int l, hipStream_t s)
-{
-    const int64_t n = 2 * (int64_t)p.lev[l].np;
-    hipLaunchKernelGGL(k_l2l, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l);
+    const int t = p.span_top[i], nl = p.span_n[i];
+    const int64_t n = 8 << t;
+    hipLaunchKernelGGL(k_l2l_span, dim3(grid_x8(n * n * n)), dim3(nl == 3 ? L2L_SPAN_WG : 64), 0, s, p, t, nl);
     return hipGetLastError();
 }
 
@@ -764,7 +903,7 @@ hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s)
     const Block bs = block_shape(p.npL);
     const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
     const unsigned grid = (unsigned)((((nblk + 3) / 4) + 7) / 8 * 8);   // whole rounds over the 8 XCDs
-    hipLaunchKernelGGL(k_leaf<false>, dim3(grid), dim3(WG), 0, s, p, phi, g);
+    hipLaunchKernelGGL(k_leaf<false>, dim3(grid), dim3(WG), 0, s, p, p.Kst, p.plist_leaf, phi, g);
     return hipGetLastError();
 }
 
@@ -773,7 +912,7 @@ hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s)
     const Block bs = block_shape(p.npL);
     const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
     const unsigned grid = (unsigned)((((nblk + 3) / 4) + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_leaf<true>, dim3(grid), dim3(WG), 0, s, p, drho, nullptr);
+    hipLaunchKernelGGL(k_leaf<true>, dim3(grid), dim3(WG), 0, s, p, p.Ksa, p.plist_leaf, drho, nullptr);
     return hipGetLastError();
 }
 

@@ -154,6 +154,45 @@ def test_cfg2_sampled_full_size():
     assert np.abs(F).max() / np.abs(cfg["rho"][None] * g).sum() < 1e-12
 
 
+def test_depth5_two_tree_spans():
+    """256^3 (depth 5): the M2M and L2L passes run as two spans of levels,
+    the lower span taking its roots' parent expansions from memory.  Forward
+    on sampled sinks and the adjoint on one z-layer against the oracle, the
+    dot-product identity on the whole grid."""
+    n, L = 256, 5
+    rng = np.random.default_rng(505)
+    rho = rng.uniform(0.0, 1.0, (n, n, n))
+    w = rng.standard_normal((n, n, n))
+    u = rng.standard_normal((3, n, n, n))
+    lay = W.uniform_layout(L)
+    plan = fmm.Plan(lay)
+    assert plan.info()["depth"] == L
+    say("256^3 forward + adjoint")
+    rd, wd, ud = to_dev(lay, rho), to_dev(lay, w), to_dev(lay, u)
+    phi_d, g_d = plan.forward(rd)
+    dr_d = plan.adjoint(wd, ud)
+    torch.cuda.synchronize()
+    lhs = float((wd * phi_d).sum() + (ud.reshape(3, -1) * g_d).sum())
+    rhs = float((dr_d * rd).sum())
+    scale = float((wd * phi_d).abs().sum() + (ud.reshape(3, -1) * g_d).abs().sum())
+    assert abs(lhs - rhs) / scale < 1e-12
+    phi = lay.layout_to_dense(phi_d.cpu().numpy())
+    g = lay.layout_to_dense(g_d.cpu().numpy())
+    dr = lay.layout_to_dense(dr_d.cpu().numpy())
+    del rd, wd, ud, phi_d, g_d, dr_d
+    sinks = np.concatenate([rng.choice(n ** 3, 256, replace=False),
+                            [0, n - 1, n ** 3 - 1, (128 * n + 127) * n + 128]]).astype(np.int64)
+    say("oracle sinks", sinks.size)
+    po, go = O.fmm_sinks(rho, sinks)
+    assert np.abs(phi.reshape(-1)[sinks] - po).max() / np.abs(phi).max() < TOL
+    gg = g.reshape(3, -1)[:, sinks]
+    assert np.sqrt(((gg - go) ** 2).sum(0)).max() / np.sqrt((g ** 2).sum(0)).max() < TOL
+    z = 131
+    say("oracle adjoint, z-layer", z)
+    do = O.fmm_adjoint(w, u, zslab=(z, z + 1))
+    assert np.abs(dr[z] - do[z]).max() / np.abs(do[z]).max() < TOL
+
+
 def test_deterministic_bitwise():
     cfg = W.cfg5_lognormal()
     lay = W.uniform_layout(cfg["L"])
