@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-slab", type=int, default=16,
+    ap.add_argument("--cpu-slab", type=int, default=64,
                     help="leaf z-layers of the 128^3 grid in the CPU-oracle sample (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before warmup, copy this many MiB device to device once: a plain copy "
