@@ -58,16 +58,22 @@ def read_traffic(phase: str):
 
 
 def phase_flops(phase: str, info: dict) -> float:
+    """Algorithmic FLOP of one launch group of a phase.  The upward phases
+    hold the P2M and the M2M of the levels up to three above the leaves
+    (cells of levels max(1, L-4)..L-1 are shifted to their parents); the
+    m2m phase holds the rest; the l2l phase the shifts into levels 1..L-2
+    (the leaf phases form level L-1)."""
     N = info["n_leaf_cells"]
     L = info["depth"]
-    inner = sum((8 << l) ** 3 for l in range(1, L))
+    cells = lambda lo, hi: sum((8 << l) ** 3 for l in range(lo, hi))   # noqa: E731
+    m2m_low = 168.0 * cells(max(1, L - 4), L)
     return {"m2l": 168.0 * info["m2l_pairs"],
-            "leaf": 8.0 * info["p2p_pairs"] + 100.0 * N,
-            "leaf_adj": 8.0 * info["p2p_pairs"] + 40.0 * N,
-            "upward_leaf": 40.0 * N,
-            "upward_leaf_adj": 100.0 * N,
-            "m2m": 168.0 * inner,
-            "l2l": 168.0 * inner}[phase]
+            "leaf": 8.0 * info["p2p_pairs"] + 100.0 * N + 168.0 * cells(L - 1, L),
+            "leaf_adj": 8.0 * info["p2p_pairs"] + 40.0 * N + 168.0 * cells(L - 1, L),
+            "upward_leaf": 40.0 * N + m2m_low,
+            "upward_leaf_adj": 100.0 * N + m2m_low,
+            "m2m": 168.0 * cells(1, max(1, L - 4)),
+            "l2l": 168.0 * cells(1, L - 1)}[phase]
 
 
 def main():
@@ -148,7 +154,7 @@ def main():
     traffic = read_traffic(dom)
     per_phase = {k: {"avg_ms": v["ms"] / v["events"], "share": v["ms"] / (1e3 * elapsed),
                      "tflops": phase_flops(k, info) * v["launches"] / v["events"] / (v["ms"] / v["events"] * 1e-3) / 1e12
-                     if k not in ("m2m", "l2l") else None}
+                     }
                  for k, v in phases.items()}
 
     out = {

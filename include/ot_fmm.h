@@ -134,12 +134,12 @@ const char *ot_fmm_last_error(void);   /* message of this thread's last failure 
  * events on its stream around each kernel phase (at most max_calls calls are
  * recorded).  timing_end waits for the last event and reports, per phase, the
  * number of timed launches and their summed duration. */
-#define OT_FMM_PHASE_UPWARD_LEAF      0   /* P2M + first M2M, forward */
-#define OT_FMM_PHASE_M2M              1   /* M2M, levels L-2..0 (all launches of a call) */
+#define OT_FMM_PHASE_UPWARD_LEAF      0   /* P2M + M2M of up to 3 levels above the leaves, forward */
+#define OT_FMM_PHASE_M2M              1   /* M2M of the remaining levels, L-5..0 (none at depth <= 4) */
 #define OT_FMM_PHASE_M2L              2   /* M2L, all levels, one launch */
-#define OT_FMM_PHASE_L2L              3   /* L2L, levels 1..L-1 (all launches of a call) */
+#define OT_FMM_PHASE_L2L              3   /* M2L sums + L2L, levels 0..L-2 (level L-1: leaf phase) */
 #define OT_FMM_PHASE_LEAF             4   /* leaf P2P + L2P, forward */
-#define OT_FMM_PHASE_UPWARD_LEAF_ADJ  5
+#define OT_FMM_PHASE_UPWARD_LEAF_ADJ  5   /* P2M of the dual sources + M2M of up to 3 levels, adjoint */
 #define OT_FMM_PHASE_LEAF_ADJ         6
 #define OT_FMM_PHASE_TOTAL            7   /* whole forward or adjoint call */
 #define OT_FMM_NUM_PHASES             8

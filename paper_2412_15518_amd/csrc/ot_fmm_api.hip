@@ -546,16 +546,16 @@ struct DeviceGuard {
     }
 };
 
-// M2M over the levels L-2..0, the M2L of every level, and the L2L down to
-// level L-2; the forward and the adjoint share them (the leaf stages differ)
+// the M2M spans above the bottom one (the bottom span runs fused with the
+// P2M), the M2L of every level, and the L2L down to level L-2; the forward
+// and the adjoint share them (the leaf stages differ)
 hipError_t tree_passes(ot_fmm_plan P, hipStream_t s)
 {
     const DevPlan &d = P->dp;
     hipError_t e = hipSuccess;
-    if (d.n_span > 0) {
-        Phase ph(P, s, OT_FMM_PHASE_M2M, d.n_span);
-        for (int i = d.n_span - 1; i >= 0; --i)
-            if ((e = launch_m2m_span(d, i, s)) != hipSuccess) return e;
+    if (d.n_span > 1) {
+        Phase ph(P, s, OT_FMM_PHASE_M2M, d.n_span - 1);
+        if ((e = launch_m2m_upper(d, s)) != hipSuccess) return e;
         ph.end();
     }
     if (P->L >= 1) {
@@ -697,7 +697,7 @@ int ot_fmm_adjoint(ot_fmm_plan P, const double *dphi, const double *dg, double *
     hipError_t e;
     Phase total(P, s, OT_FMM_PHASE_TOTAL, 0);
     {
-        Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF_ADJ, 1);
+        Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF_ADJ, d.n_span > 0 ? 2 : 1);
         if ((e = launch_upward_leaf_adj(d, dphi, dg, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf_adj");
         ph.end();
     }

@@ -127,9 +127,10 @@ struct ot_fmm_plan_s {
 namespace otfmm {
 
 // kernel launchers (ot_fmm_kernels.hip); each returns hipGetLastError()
+// P2M into level L-1 fused with the bottom M2M span (or plain P2M at depth <= 1)
 hipError_t launch_upward_leaf(const DevPlan &p, const double *rho, hipStream_t s);
 hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const double *u, hipStream_t s);
-hipError_t launch_m2m_span(const DevPlan &p, int span, hipStream_t s);
+hipError_t launch_m2m_upper(const DevPlan &p, hipStream_t s);      // the M2M spans above the bottom one
 hipError_t launch_m2l(const DevPlan &p, hipStream_t s);
 hipError_t m2l_blocks_per_cu(int *n);   // resident M2L workgroups per CU
 hipError_t launch_l2l_span(const DevPlan &p, int span, hipStream_t s);

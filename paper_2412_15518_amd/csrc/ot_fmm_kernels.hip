@@ -221,17 +221,15 @@ __host__ __device__ inline Block block_shape(int np)
 }
 
 // ------------------------------------------------------------------------
-// P2M + M2M into level L-1 (forward): lane = one leaf parent Q
+// P2M and the first M2M, for one leaf parent Q (a cell of level L-1): stages
+// Q's 8 leaf sources into the padded source planes and returns Q's scaled
+// moments.  Forward: point masses m = rho h^3.  Adjoint: the dual sources, a
+// monopole w and a scaled dipole +u at each leaf centre.
 // ------------------------------------------------------------------------
 template <bool ADJ>
-__global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const double *__restrict__ a0,
-                                                    const double *__restrict__ a1)
+__device__ __forceinline__ void leaf_p2m(const DevPlan &p, const double *__restrict__ a0,
+                                         const double *__restrict__ a1, int Qx, int Qy, int Qz, double *Mq)
 {
-    const int npL = p.npL;
-    const int64_t nQ = (int64_t)npL * npL * npL;
-    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (t >= nQ) return;
-    const int Qx = (int)(t % npL), Qy = (int)((t / npL) % npL), Qz = (int)(t / ((int64_t)npL * npL));
     const int64_t ppL3 = (int64_t)p.ppL * p.ppL * p.ppL;
     const int64_t padQ = ((int64_t)(Qz + p.hpL) * p.ppL + (Qy + p.hpL)) * p.ppL + (Qx + p.hpL);
     const int sx = Qx >> 2, sy = Qy >> 2, sz = Qz >> 2;
@@ -239,7 +237,6 @@ __global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const doubl
     const int lx0 = (2 * Qx) & 7, ly0 = (2 * Qy) & 7, lz0 = (2 * Qz) & 7;
     const int64_t N = p.n_leaf_cells;
     const double hh = 0.5 * p.hleaf;
-    double Mq[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) Mq[k] = 0.0;
 #pragma unroll
@@ -265,13 +262,35 @@ __global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const doubl
             dipole_apply(Mq, e, u);
         }
     }
+}
+
+// moments of cell c of level l, stored under its parent c >> 1
+__device__ __forceinline__ double *moment_slot(const DevLevel &D, int cx, int cy, int cz)
+{
+    const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+    const int64_t pp = D.pp;
+    const int64_t pad = ((int64_t)((cz >> 1) + D.hp) * pp + ((cy >> 1) + D.hp)) * pp + ((cx >> 1) + D.hp);
+    return D.M + (int64_t)bs * pp * pp * pp + pad;
+}
+
+// P2M + M2M into level L-1 when no level lies between it and the root
+// (depth 0 and 1): lane = one leaf parent Q
+template <bool ADJ>
+__global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const double *__restrict__ a0,
+                                                    const double *__restrict__ a1)
+{
+    const int npL = p.npL;
+    const int64_t nQ = (int64_t)npL * npL * npL;
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= nQ) return;
+    const int Qx = (int)(t % npL), Qy = (int)((t / npL) % npL), Qz = (int)(t / ((int64_t)npL * npL));
+    double Mq[NC];
+    leaf_p2m<ADJ>(p, a0, a1, Qx, Qy, Qz, Mq);
     if (p.L >= 1) {
-        const DevLevel &D = p.lev[p.L - 1];
-        const int bself = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
-        const int64_t pp3 = (int64_t)D.pp * D.pp * D.pp;
-        const int64_t padq = ((int64_t)((Qz >> 1) + D.hp) * D.pp + ((Qy >> 1) + D.hp)) * D.pp + ((Qx >> 1) + D.hp);
+        double *out = moment_slot(p.lev[p.L - 1], Qx, Qy, Qz);
+        const int64_t pp = p.lev[p.L - 1].pp, cs = 8 * pp * pp * pp;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) D.M[(k * 8 + bself) * pp3 + padq] = Mq[k];
+        for (int k = 0; k < NC; ++k) out[k * cs] = Mq[k];
     }
 }
 
@@ -313,11 +332,16 @@ __device__ __forceinline__ void span_cell(int ax, int ay, int az, int j, int idx
 // M2M, deepest level of the span first.  Thread t = (cell ci, child b) of a
 // step shifts the moments of child b to the centre of cell ci; the 8
 // children of a cell sit in 8 consecutive lanes and are summed by shuffles
-// in a fixed order.  Children of the deepest cells come from memory, the
-// others from the previous step through LDS.
+// in a fixed order.  The children of the deepest cells come from memory
+// (SRC = 0), or, for the bottom span of the forward pass, are the leaf
+// parents themselves, whose moments thread t forms by P2M from the leaf
+// masses and stores (SRC = 1); the other steps take their children from the
+// previous step through LDS.
 constexpr int M2M_SPAN_WG = 512;
 
-__global__ __launch_bounds__(M2M_SPAN_WG) void k_m2m_span(const DevPlan p, int ltop, int nlev)
+template <int SRC>
+__global__ __launch_bounds__(M2M_SPAN_WG) __attribute__((amdgpu_waves_per_eu(4))) void k_m2m_span(const DevPlan p, const double *__restrict__ a0,
+                                                          const double *__restrict__ a1, int ltop, int nlev)
 {
     __shared__ double Ms[2][64][NC];      // moments of the span's cells at depths 1 and 2
     const int n = 8 << ltop;
@@ -335,7 +359,16 @@ __global__ __launch_bounds__(M2M_SPAN_WG) void k_m2m_span(const DevPlan p, int l
 #pragma unroll
         for (int k = 0; k < NC; ++k) Mc[k] = 0.0;
         if (act) {
-            if (j == nlev - 1) {
+            if (j == nlev - 1 && SRC == 1) {
+                // the child is a leaf parent: P2M from its leaf masses, stored for the M2L
+                const int Qx = 2 * cx + (b & 1), Qy = 2 * cy + ((b >> 1) & 1), Qz = 2 * cz + (b >> 2);
+                leaf_p2m<false>(p, a0, a1, Qx, Qy, Qz, Mc);
+                const DevLevel &Dc = p.lev[lv + 1];
+                double *out = moment_slot(Dc, Qx, Qy, Qz);
+                const int64_t cs = 8 * (int64_t)Dc.pp * Dc.pp * Dc.pp;
+#pragma unroll
+                for (int k = 0; k < NC; ++k) out[k * cs] = Mc[k];
+            } else if (j == nlev - 1) {
                 // the children of c are stored under c in level lv + 1
                 const DevLevel &Dc = p.lev[lv + 1];
                 const int64_t pp = Dc.pp, pp3 = pp * pp * pp;
@@ -365,11 +398,10 @@ __global__ __launch_bounds__(M2M_SPAN_WG) void k_m2m_span(const DevPlan p, int l
                 for (int k = 0; k < NC; ++k) Ms[j & 1][ci][k] = Mp[k];
             }
             const DevLevel &D = p.lev[lv];
-            const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
-            const int64_t pp = D.pp, pp3 = pp * pp * pp;
-            const int64_t pad = ((int64_t)((cz >> 1) + D.hp) * pp + ((cy >> 1) + D.hp)) * pp + ((cx >> 1) + D.hp);
+            double *out = moment_slot(D, cx, cy, cz);
+            const int64_t cs = 8 * (int64_t)D.pp * D.pp * D.pp;
 #pragma unroll
-            for (int k = 0; k < NC; ++k) D.M[(k * 8 + bs) * pp3 + pad] = Mp[k];
+            for (int k = 0; k < NC; ++k) out[k * cs] = Mp[k];
         }
         __syncthreads();
     }
@@ -852,29 +884,56 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
 // launchers
 // ------------------------------------------------------------------------
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
+static inline unsigned grid_x8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
+
+// upward pass up to the bottom M2M span.  Forward: P2M into level L-1 fused
+// with the bottom span.  Adjoint: its P2M moves four planes each way per leaf
+// cell, which a fused launch would serialise with the span's reduction, so it
+// runs as its own launch followed by the span.  Depths 0 and 1 have no span.
+static hipError_t launch_upward_leaf(const DevPlan &p, int src, const double *a0, const double *a1, hipStream_t s)
+{
+    const int last = p.n_span - 1;
+    const int64_t nq = (int64_t)p.npL * p.npL * p.npL;
+    if (last < 0 || src == 2) {
+        if (src == 1)
+            hipLaunchKernelGGL(k_upward_leaf<false>, dim3(grid_for(nq)), dim3(WG), 0, s, p, a0, a1);
+        else
+            hipLaunchKernelGGL(k_upward_leaf<true>, dim3(grid_for(nq)), dim3(WG), 0, s, p, a0, a1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || last < 0) return e;
+    }
+    const int t = p.span_top[last], nl = p.span_n[last];
+    const int64_t n = 8 << t;
+    const dim3 grid(grid_x8(n * n * n)), block(nl == 3 ? M2M_SPAN_WG : 64);
+    if (src == 1)
+        hipLaunchKernelGGL(k_m2m_span<1>, grid, block, 0, s, p, a0, a1, t, nl);
+    else
+        hipLaunchKernelGGL(k_m2m_span<0>, grid, block, 0, s, p, nullptr, nullptr, t, nl);
+    return hipGetLastError();
+}
 
 hipError_t launch_upward_leaf(const DevPlan &p, const double *rho, hipStream_t s)
 {
-    const int64_t n = (int64_t)p.npL * p.npL * p.npL;
-    hipLaunchKernelGGL(k_upward_leaf<false>, dim3(grid_for(n)), dim3(WG), 0, s, p, rho, nullptr);
-    return hipGetLastError();
+    return launch_upward_leaf(p, 1, rho, nullptr, s);
 }
 
 hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const double *u, hipStream_t s)
 {
-    const int64_t n = (int64_t)p.npL * p.npL * p.npL;
-    hipLaunchKernelGGL(k_upward_leaf<true>, dim3(grid_for(n)), dim3(WG), 0, s, p, w, u);
-    return hipGetLastError();
+    return launch_upward_leaf(p, 2, w, u, s);
 }
 
-static inline unsigned grid_x8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
-
-hipError_t launch_m2m_span(const DevPlan &p, int i, hipStream_t s)
+// the M2M spans above the bottom one, deepest first
+hipError_t launch_m2m_upper(const DevPlan &p, hipStream_t s)
 {
-    const int t = p.span_top[i], nl = p.span_n[i];
-    const int64_t n = 8 << t;
-    hipLaunchKernelGGL(k_m2m_span, dim3(grid_x8(n * n * n)), dim3(nl == 3 ? M2M_SPAN_WG : 64), 0, s, p, t, nl);
-    return hipGetLastError();
+    for (int i = p.n_span - 2; i >= 0; --i) {
+        const int t = p.span_top[i], nl = p.span_n[i];
+        const int64_t n = 8 << t;
+        hipLaunchKernelGGL(k_m2m_span<0>, dim3(grid_x8(n * n * n)), dim3(nl == 3 ? M2M_SPAN_WG : 64), 0, s, p,
+                           nullptr, nullptr, t, nl);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_m2l(const DevPlan &p, hipStream_t s)
