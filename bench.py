@@ -153,7 +153,7 @@ def main():
     achieved = fl_launch / (avg_ms * 1e-3) / 1e12
     traffic = read_traffic(dom)
     per_phase = {k: {"avg_ms": v["ms"] / v["events"], "share": v["ms"] / (1e3 * elapsed),
-                     "tflops": phase_flops(k, info) * v["launches"] / v["events"] / (v["ms"] / v["events"] * 1e-3) / 1e12
+                     "tflops": phase_flops(k, info) / (v["ms"] / v["events"] * 1e-3) / 1e12
                      }
                  for k, v in phases.items()}
 
