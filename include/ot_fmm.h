@@ -63,6 +63,16 @@ extern "C" {
 #define OT_FMM_HOST_ONLY  (1u << 0)  /* validate and build host tables only: no
                                         device memory; plan_info works, forward
                                         and adjoint return OT_FMM_NO_DEVICE_STATE */
+#define OT_FMM_M2L_FP32   (1u << 1)  /* M2L (forward and adjoint) in FP32: moments
+                                        and derivative tensors rounded to FP32, the
+                                        products of each parent offset summed in
+                                        FP32 and then added to FP64 accumulators;
+                                        every other stage stays FP64.  The paper's
+                                        runs are FP64 (its data-set table, Sec. 6.1):
+                                        this is an optional faster M2L whose result
+                                        differs from the FP64 one by about 1e-7
+                                        normwise (bounded by 1e-5 in the tests).
+                                        Moments must stay inside the FP32 range. */
 
 typedef struct ot_fmm_plan_s *ot_fmm_plan;   /* opaque */
 

@@ -468,12 +468,18 @@ int setup_device(ot_fmm_plan P)
     if ((rc = dev_upload(P, &d.Kst, P->Kst))) return rc;
     if ((rc = dev_upload(P, &d.Ksa, P->Ksa))) return rc;
     if ((rc = dev_upload(P, &d.Dtab, P->Dtab))) return rc;
+    d.m2l_fp32 = (P->flags & OT_FMM_M2L_FP32) ? 1 : 0;
+    d.Dtab32 = nullptr;
+    if (d.m2l_fp32) {
+        P->Dtab32.assign(P->Dtab.begin(), P->Dtab.end());    // rounded to nearest
+        if ((rc = dev_upload(P, &d.Dtab32, P->Dtab32))) return rc;
+    }
     if ((rc = dev_upload(P, &d.plist_near, P->plist_near))) return rc;
     if ((rc = dev_upload(P, &d.plist_cube, P->plist_cube))) return rc;
     int ncu = 0, per_cu = 0;
     if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device)) != hipSuccess)
         return hip_fail(e, "hipDeviceGetAttribute");
-    if ((e = m2l_blocks_per_cu(&per_cu)) != hipSuccess) return hip_fail(e, "occupancy of the M2L kernel");
+    if ((e = m2l_blocks_per_cu(d.m2l_fp32, &per_cu)) != hipSuccess) return hip_fail(e, "occupancy of the M2L kernel");
     build_m2l_schedule(P, std::max(1, ncu * std::max(1, per_cu)));
     if ((rc = dev_upload(P, &d.mdesc, P->mdesc))) return rc;
     d.n_plist_near = (int)P->plist_near.size();
@@ -496,6 +502,8 @@ int setup_device(ot_fmm_plan P)
         v.nby = v.np / v.by;
         const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;
         if ((rc = dev_alloc(P, &v.M, (size_t)NC * 8 * pp3, true))) return rc;
+        v.M32 = nullptr;
+        if (d.m2l_fp32 && (rc = dev_alloc(P, &v.M32, (size_t)NC * 8 * pp3, true))) return rc;
         if (l < L - 1 && (rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
@@ -606,7 +614,7 @@ int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order, 
 {
     if (!out) return fail(OT_FMM_INVALID_ARGUMENT, "out is NULL");
     *out = nullptr;
-    if (flags & ~OT_FMM_HOST_ONLY) return fail(OT_FMM_INVALID_ARGUMENT, "unknown flag bits");
+    if (flags & ~(OT_FMM_HOST_ONLY | OT_FMM_M2L_FP32)) return fail(OT_FMM_INVALID_ARGUMENT, "unknown flag bits");
     if (!std::isfinite(theta) || theta <= 0.0) return fail(OT_FMM_INVALID_ARGUMENT, "theta must be finite and > 0");
     if (!(theta > 1.0 / 3.0 && theta <= 1.0))
         return fail(OT_FMM_UNSUPPORTED_THETA, "theta must lie in (1/3, 1] (near radius 1/theta in [1, 3) cells)");

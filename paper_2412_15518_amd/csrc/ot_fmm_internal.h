@@ -46,6 +46,7 @@ struct DevLevel {
     int nbx, nby;    // blocks per axis in x and y
     double h;        // cell width of this level
     double *M;       // [NC][8][pp^3]
+    float *M32;      // FP32 copy of M for the FP32 M2L (null unless the plan asks for it)
     double *C;       // [NC][8][np^3] local coefficients (final); null at level L-1
     double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
 };
@@ -79,6 +80,8 @@ struct DevPlan {
     const double *Ksa;          // [4][n_plist_leaf][27]: the same rows plane by plane for the
                                 //   adjoint leaf pass: K0, then -K1x, -K1y, -K1z
     const double *Dtab;         // [L][OFF_N][NC]: derivative tensor of -G/r per level
+    const float *Dtab32;        // the same in FP32 (FP32 M2L only)
+    int m2l_fp32;               // 1: the M2L runs in FP32 with FP64 accumulation
     const char4 *plist_leaf; int n_plist_leaf;   // parent offsets of the leaf P2P
     const char4 *plist_near; int n_plist_near;   // |P| <= 1/theta (levels >= 1)
     const char4 *plist_cube; int n_plist_cube;   // [-3,3]^3 (root level)
@@ -116,6 +119,7 @@ struct ot_fmm_plan_s {
     std::vector<char4> plist_near, plist_cube;
     std::vector<otfmm::M2LDesc> mdesc;
     std::vector<double> Ktab, Kst, Ksa, Dtab;
+    std::vector<float> Dtab32;
     ot_fmm_info info{};
 
     // device state
@@ -132,7 +136,7 @@ hipError_t launch_upward_leaf(const DevPlan &p, const double *rho, hipStream_t s
 hipError_t launch_upward_leaf_adj(const DevPlan &p, const double *w, const double *u, hipStream_t s);
 hipError_t launch_m2m_upper(const DevPlan &p, hipStream_t s);      // the M2M spans above the bottom one
 hipError_t launch_m2l(const DevPlan &p, hipStream_t s);
-hipError_t m2l_blocks_per_cu(int *n);   // resident M2L workgroups per CU
+hipError_t m2l_blocks_per_cu(int fp32, int *n);   // resident M2L workgroups per CU
 hipError_t launch_l2l_span(const DevPlan &p, int span, hipStream_t s);
 hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s);
 hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s);

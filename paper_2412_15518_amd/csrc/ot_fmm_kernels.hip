@@ -264,13 +264,20 @@ __device__ __forceinline__ void leaf_p2m(const DevPlan &p, const double *__restr
     }
 }
 
-// moments of cell c of level l, stored under its parent c >> 1
-__device__ __forceinline__ double *moment_slot(const DevLevel &D, int cx, int cy, int cz)
+// store the moments of cell c of level l (kept under its parent c >> 1),
+// and their FP32 copy when the FP32 M2L needs one
+__device__ __forceinline__ void store_moments(const DevLevel &D, int cx, int cy, int cz, const double *Mq)
 {
     const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
-    const int64_t pp = D.pp;
+    const int64_t pp = D.pp, pp3 = pp * pp * pp;
     const int64_t pad = ((int64_t)((cz >> 1) + D.hp) * pp + ((cy >> 1) + D.hp)) * pp + ((cx >> 1) + D.hp);
-    return D.M + (int64_t)bs * pp * pp * pp + pad;
+    const int64_t at = (int64_t)bs * pp3 + pad, cs = 8 * pp3;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) D.M[at + k * cs] = Mq[k];
+    if (D.M32) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) D.M32[at + k * cs] = (float)Mq[k];
+    }
 }
 
 // P2M + M2M into level L-1 when no level lies between it and the root
@@ -286,12 +293,7 @@ __global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const doubl
     const int Qx = (int)(t % npL), Qy = (int)((t / npL) % npL), Qz = (int)(t / ((int64_t)npL * npL));
     double Mq[NC];
     leaf_p2m<ADJ>(p, a0, a1, Qx, Qy, Qz, Mq);
-    if (p.L >= 1) {
-        double *out = moment_slot(p.lev[p.L - 1], Qx, Qy, Qz);
-        const int64_t pp = p.lev[p.L - 1].pp, cs = 8 * pp * pp * pp;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) out[k * cs] = Mq[k];
-    }
+    if (p.L >= 1) store_moments(p.lev[p.L - 1], Qx, Qy, Qz, Mq);
 }
 
 typedef __attribute__((address_space(1))) double gdouble;   // global memory
@@ -363,11 +365,7 @@ __global__ __launch_bounds__(M2M_SPAN_WG) __attribute__((amdgpu_waves_per_eu(4))
                 // the child is a leaf parent: P2M from its leaf masses, stored for the M2L
                 const int Qx = 2 * cx + (b & 1), Qy = 2 * cy + ((b >> 1) & 1), Qz = 2 * cz + (b >> 2);
                 leaf_p2m<false>(p, a0, a1, Qx, Qy, Qz, Mc);
-                const DevLevel &Dc = p.lev[lv + 1];
-                double *out = moment_slot(Dc, Qx, Qy, Qz);
-                const int64_t cs = 8 * (int64_t)Dc.pp * Dc.pp * Dc.pp;
-#pragma unroll
-                for (int k = 0; k < NC; ++k) out[k * cs] = Mc[k];
+                store_moments(p.lev[lv + 1], Qx, Qy, Qz, Mc);
             } else if (j == nlev - 1) {
                 // the children of c are stored under c in level lv + 1
                 const DevLevel &Dc = p.lev[lv + 1];
@@ -397,11 +395,7 @@ __global__ __launch_bounds__(M2M_SPAN_WG) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
                 for (int k = 0; k < NC; ++k) Ms[j & 1][ci][k] = Mp[k];
             }
-            const DevLevel &D = p.lev[lv];
-            double *out = moment_slot(D, cx, cy, cz);
-            const int64_t cs = 8 * (int64_t)D.pp * D.pp * D.pp;
-#pragma unroll
-            for (int k = 0; k < NC; ++k) out[k * cs] = Mp[k];
+            store_moments(p.lev[lv], cx, cy, cz, Mp);
         }
         __syncthreads();
     }
@@ -556,6 +550,179 @@ __global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *_
         }
         if (++ct == TPP) {
             ct = 0;
+            if (++ci == nP) {                   // block complete: store its piece
+                flush();
+                piece = 0;
+                ci = 0;
+                ++cb;
+            }
+        }
+        if (k + 1 < ntiles) stash(buf ^ 1, reg);
+        __syncthreads();
+    }
+    if (ci != 0 || ct != 0) flush();            // run ended inside a block
+}
+
+// M2L in FP32 (plan flag OT_FMM_M2L_FP32).  The schedule, the work mapping
+// and the partial sums are those of k_m2l; the moments and derivative rows
+// are FP32, the LDS tile holds four components per 16-byte read, and the 84
+// products of a pair are accumulated in FP32 over one parent offset (the 8
+// source children of a unit) and then added to FP64 accumulators, which the
+// pieces receive.
+template <int B, int... I>
+__device__ __forceinline__ void m2l1f_component(float *C, const float *D, float m, std::integer_sequence<int, I...>)
+{
+    constexpr Terms<84> T = make_sum_terms_by_source();
+    constexpr int o = source_begin(B);
+    ((C[T.t[o + I].i] = fmaf(D[T.t[o + I].k], m, C[T.t[o + I].i])), ...);
+}
+
+template <int Q>
+__device__ __forceinline__ void m2l1f_quad(float *C, const float *D, float4 m)
+{
+    m2l1f_component<4 * Q>(C, D, m.x, std::make_integer_sequence<int, terms_of_source(4 * Q)>{});
+    m2l1f_component<4 * Q + 1>(C, D, m.y, std::make_integer_sequence<int, terms_of_source(4 * Q + 1)>{});
+    m2l1f_component<4 * Q + 2>(C, D, m.z, std::make_integer_sequence<int, terms_of_source(4 * Q + 2)>{});
+    m2l1f_component<4 * Q + 3>(C, D, m.w, std::make_integer_sequence<int, terms_of_source(4 * Q + 3)>{});
+}
+
+template <int... Q>
+__device__ __forceinline__ void m2l1f_child(float *C, const float *D, const float4 *rows, int lane,
+                                            std::integer_sequence<int, Q...>)
+{
+    // rows[q * 64 + lane] = components 4q .. 4q + 3 of the lane's source
+    (m2l1f_quad<Q>(C, D, rows[Q * 64 + lane]), ...);
+}
+
+constexpr int M2LF_QUADS = M2L_TBP * NC / 4;                  // (child, 4 components) rows per tile
+constexpr int M2LF_QUADS_PER_WAVE = (M2LF_QUADS + 7) / 8;     // at most
+
+__global__ __launch_bounds__(M2L_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32,
+                                                    const char4 *__restrict__ near, const char4 *__restrict__ cube,
+                                                    const M2LDesc *__restrict__ descs)
+{
+    // [buffer][child of the tile][component quad][lane] -> 4 components
+    __shared__ float4 tile[2][M2L_TBP][NC / 4][64];
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g >= p.n_mdesc) return;
+    const M2LDesc d = descs[g];
+    const int lev = d.level;
+    const DevLevel &D = p.lev[lev];
+    const int lane = threadIdx.x & 63;
+    const int b = uniform(threadIdx.x >> 6);        // this wave's sink child
+    const int r2i = p.r2i;
+    const int nP = lev == 0 ? p.n_plist_cube : p.n_plist_near;
+    const char4 *__restrict__ plist = lev == 0 ? cube : near;
+    const float *__restrict__ Dl = Dtab32 + (size_t)lev * OFF_N * NC;
+    const int np = D.np, pp = D.pp, hp = D.hp;
+    const int pp3 = pp * pp * pp, np3 = np * np * np;
+    const int lx = lane & (D.bx - 1), ly = (lane / D.bx) & (D.by - 1), lz = lane / (D.bx * D.by);
+    auto lane_xyz = [&](int blk, int &qx, int &qy, int &qz) {
+        qx = (blk % D.nbx) * D.bx + lx;
+        qy = ((blk / D.nbx) % D.nby) * D.by + ly;
+        qz = (blk / (D.nbx * D.nby)) * D.bz + lz;
+    };
+    auto lane_q = [&](int blk) {
+        int qx, qy, qz;
+        lane_xyz(blk, qx, qy, qz);
+        return (qz * np + qy) * np + qx;
+    };
+    auto lane_mq = [&](int blk) {
+        int qx, qy, qz;
+        lane_xyz(blk, qx, qy, qz);
+        return ((qz + hp) * pp + (qy + hp)) * pp + (qx + hp);
+    };
+    constexpr int TPP = 8 / M2L_TBP;                // tiles per unit
+    const int ntiles = (d.uend - d.ubeg) * TPP;
+
+    // fetch cursor as in k_m2l; wave w stages quad rows r = w + 8 u (child
+    // r / 5, components 4 (r % 5) .. + 3) of its lane's source, one 16-byte
+    // LDS write each
+    int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
+    int fmq = lane_mq(fb);
+    auto fetch = [&](float *reg) {
+        const char4 P = plist[fi];
+        const float *src = D.M32 + (fmq + ft * M2L_TBP * pp3 + (P.z * pp + P.y) * pp + P.x);
+#pragma unroll
+        for (int u = 0; u < M2LF_QUADS_PER_WAVE; ++u) {
+            const int r = b + 8 * u;
+            const int off = ((4 * (r % 5)) * 8 + r / 5) * pp3;
+            if (r < M2LF_QUADS) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) reg[4 * u + c] = src[off + c * 8 * pp3];
+            }
+        }
+    };
+    auto stash = [&](int buf, const float *reg) {
+#pragma unroll
+        for (int u = 0; u < M2LF_QUADS_PER_WAVE; ++u) {
+            const int r = b + 8 * u;
+            if (r < M2LF_QUADS)
+                tile[buf][r / 5][r % 5][lane] = make_float4(reg[4 * u], reg[4 * u + 1], reg[4 * u + 2], reg[4 * u + 3]);
+        }
+    };
+
+    int cb = fb, ci = fi, ct = 0;
+    int piece = d.piece0;
+
+    double C[NC];           // FP64 accumulators of the block
+    float Cf[NC];           // FP32 sum of the current parent offset
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        C[k] = 0.0;
+        Cf[k] = 0.0f;
+    }
+    auto fold = [&]() {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            C[k] += (double)Cf[k];
+            Cf[k] = 0.0f;
+        }
+    };
+    auto flush = [&]() {
+        fold();
+        double *out = D.Cp + (size_t)piece * NC * 8 * np3 + lane_q(cb);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            out[(size_t)(k * 8 + b) * np3] = C[k];
+            C[k] = 0.0;
+        }
+    };
+
+    float reg[4 * M2LF_QUADS_PER_WAVE];
+    fetch(reg);
+    stash(0, reg);
+    __syncthreads();
+
+    for (int k = 0; k < ntiles; ++k) {
+        if (k + 1 < ntiles) {
+            if (++ft == TPP) {
+                ft = 0;
+                if (++fi == nP) {
+                    fi = 0;
+                    fmq = lane_mq(++fb);
+                }
+            }
+            fetch(reg);
+        }
+        const int buf = k & 1;
+        const char4 P = plist[ci];
+        const int bp0 = ct * M2L_TBP;
+#pragma unroll
+        for (int i = 0; i < M2L_TBP; ++i) {
+            const int bp = bp0 + i;
+            const int ox = 2 * P.x + (bp & 1) - (b & 1), oy = 2 * P.y + ((bp >> 1) & 1) - ((b >> 1) & 1),
+                      oz = 2 * P.z + (bp >> 2) - (b >> 2);
+            if (ox * ox + oy * oy + oz * oz <= r2i) continue;       // near: handled one level down
+            const float *Dr = Dl + off_index(ox, oy, oz) * NC;
+            float Dv[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) Dv[q] = Dr[q];
+            m2l1f_child(Cf, Dv, &tile[buf][i][0][0], lane, std::make_integer_sequence<int, NC / 4>{});
+        }
+        if (++ct == TPP) {
+            ct = 0;
+            fold();                             // one parent offset done
             if (++ci == nP) {                   // block complete: store its piece
                 flush();
                 piece = 0;
@@ -940,12 +1107,17 @@ hipError_t launch_m2l(const DevPlan &p, hipStream_t s)
 {
     if (p.n_mdesc == 0) return hipSuccess;
     const unsigned grid = (unsigned)(((p.n_mdesc + 7) / 8) * 8);     // whole rounds over the 8 XCDs
-    hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(M2L_WG), 0, s, p, p.Dtab, p.plist_near, p.plist_cube, p.mdesc);
+    if (p.m2l_fp32)
+        hipLaunchKernelGGL(k_m2l_f32, dim3(grid), dim3(M2L_WG), 0, s, p, p.Dtab32, p.plist_near, p.plist_cube,
+                           p.mdesc);
+    else
+        hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(M2L_WG), 0, s, p, p.Dtab, p.plist_near, p.plist_cube, p.mdesc);
     return hipGetLastError();
 }
 
-hipError_t m2l_blocks_per_cu(int *n)
+hipError_t m2l_blocks_per_cu(int fp32, int *n)
 {
+    if (fp32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_m2l_f32, M2L_WG, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_m2l, M2L_WG, 0);
 }
 

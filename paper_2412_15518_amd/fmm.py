@@ -27,6 +27,7 @@ DEVICE_ERROR = -7
 NO_DEVICE_STATE = -8
 FLAG_FP64 = 0
 FLAG_HOST_ONLY = 1
+FLAG_M2L_FP32 = 2
 
 NUM_PHASES = 8
 PHASES = ["upward_leaf", "m2m", "m2l", "l2l", "leaf", "upward_leaf_adj", "leaf_adj", "total"]
@@ -107,9 +108,11 @@ class Plan:
     """An FMM plan over one octree layout (see workloads.Layout).
 
     All device memory is allocated here, on the current device; forward and
-    adjoint only enqueue kernels on the current torch stream."""
+    adjoint only enqueue kernels on the current torch stream.  m2l_fp32 runs
+    the M2L in FP32 with FP64 accumulation (OT_FMM_M2L_FP32)."""
 
-    def __init__(self, layout, theta: float = 0.4, order: int = 3, host_only: bool = False):
+    def __init__(self, layout, theta: float = 0.4, order: int = 3, host_only: bool = False,
+                 m2l_fp32: bool = False):
         lib = load_library()
         self._keep = [np.ascontiguousarray(layout.level, dtype=np.int32),
                       np.ascontiguousarray(layout.coord, dtype=np.int32).reshape(-1),
@@ -126,7 +129,7 @@ class Plan:
         L.origin = (C.c_double * 3)(*[float(x) for x in layout.origin])
         L.G = float(layout.G)
         self._handle = C.c_void_p()
-        flags = FLAG_HOST_ONLY if host_only else FLAG_FP64
+        flags = (FLAG_HOST_ONLY if host_only else FLAG_FP64) | (FLAG_M2L_FP32 if m2l_fp32 else 0)
         _check(lib.ot_fmm_plan_create(C.byref(L), float(theta), int(order), flags, C.byref(self._handle)))
         self._keep = None
         self.layout = layout

@@ -95,6 +95,34 @@ def test_null_arguments():
     assert h.value is None
 
 
+def test_flags():
+    """OT_FMM_M2L_FP32 is accepted (and changes no host-side count); unknown
+    flag bits are rejected."""
+    import ctypes as C
+    lay = W.uniform_layout(2)
+    a = fmm.Plan(lay, host_only=True).info()
+    b = fmm.Plan(lay, host_only=True, m2l_fp32=True).info()
+    assert a["m2l_pairs"] == b["m2l_pairs"] and a["flops_forward"] == b["flops_forward"]
+    lib = fmm.load_library()
+    keep = [np.ascontiguousarray(lay.level, dtype=np.int32), np.ascontiguousarray(lay.coord, dtype=np.int32).reshape(-1),
+            np.ascontiguousarray(lay.parent, dtype=np.int32), np.ascontiguousarray(lay.is_leaf, dtype=np.uint8)]
+    L = fmm._Layout()
+    L.n_nodes = int(keep[0].shape[0])
+    L.level = keep[0].ctypes.data_as(C.POINTER(C.c_int32))
+    L.coord = keep[1].ctypes.data_as(C.POINTER(C.c_int32))
+    L.parent = keep[2].ctypes.data_as(C.POINTER(C.c_int32))
+    L.is_leaf = keep[3].ctypes.data_as(C.POINTER(C.c_uint8))
+    L.h_leaf_min = 1.0
+    L.origin = (C.c_double * 3)(0.0, 0.0, 0.0)
+    L.G = 1.0
+    h = C.c_void_p()
+    for bad in (1 << 2, 1 << 31):
+        assert lib.ot_fmm_plan_create(C.byref(L), 0.4, 3, fmm.FLAG_HOST_ONLY | bad, C.byref(h)) == fmm.INVALID_ARGUMENT
+        assert h.value is None
+    assert lib.ot_fmm_plan_create(C.byref(L), 0.4, 3, fmm.FLAG_HOST_ONLY | fmm.FLAG_M2L_FP32, C.byref(h)) == fmm.OK
+    lib.ot_fmm_destroy(h)
+
+
 def _expect(status, layout, theta=0.4, order=3):
     with pytest.raises(fmm.OTFMMError) as e:
         fmm.Plan(layout, theta=theta, order=order, host_only=True)
