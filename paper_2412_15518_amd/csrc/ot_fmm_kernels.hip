@@ -245,18 +245,20 @@ __device__ __forceinline__ void leaf_p2m(const DevPlan &p, const double *__restr
         const int64_t idx = base + ((lz0 + bz) * 8 + (ly0 + by)) * 8 + (lx0 + bx);
         double e[NC];
         taylor(bx ? -hh : hh, by ? -hh : hh, bz ? -hh : hh, e);    // e(z_Q - z_child)
+        // source planes [plane][parent][child]: a parent's 8 children are 64
+        // contiguous bytes
         if (!ADJ) {
             const double m = a0[idx] * p.h3;
-            p.src[b * ppL3 + padQ] = m;
+            p.src[padQ * 8 + b] = m;
 #pragma unroll
             for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], m, Mq[k]);
         } else {
             const double w = a0[idx];
             double u[3] = {a1[idx], a1[N + idx], a1[2 * N + idx]};
-            p.src[(0 * 8 + b) * ppL3 + padQ] = w;
-            p.src[(1 * 8 + b) * ppL3 + padQ] = u[0];
-            p.src[(2 * 8 + b) * ppL3 + padQ] = u[1];
-            p.src[(3 * 8 + b) * ppL3 + padQ] = u[2];
+            p.src[(0 * ppL3 + padQ) * 8 + b] = w;
+            p.src[(1 * ppL3 + padQ) * 8 + b] = u[0];
+            p.src[(2 * ppL3 + padQ) * 8 + b] = u[1];
+            p.src[(3 * ppL3 + padQ) * 8 + b] = u[2];
 #pragma unroll
             for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], w, Mq[k]);
             dipole_apply(Mq, e, u);
@@ -917,7 +919,7 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
     const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
     const int64_t pp = p.ppL;
     const int64_t ppL3 = pp * pp * pp;
-    const double *__restrict__ S = p.src + ((Qz + p.hpL) * pp + (Qy + p.hpL)) * pp + (Qx + p.hpL);
+    const double *__restrict__ S = p.src + (((Qz + p.hpL) * pp + (Qy + p.hpL)) * pp + (Qx + p.hpL)) * 8;
 
     constexpr int NA = ADJ ? 1 : 4;     // accumulators per sink child
     double acc[8][NA];
@@ -938,9 +940,13 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
         double cur[8], nxt[8];
         auto fetch = [&](int pi, double *dst) {
             const char4 P = plist[pi];
-            const double *src = S + ((int64_t)P.z * pp + P.y) * pp + P.x;
+            const double2 *src = reinterpret_cast<const double2 *>(S + (((int64_t)P.z * pp + P.y) * pp + P.x) * 8);
 #pragma unroll
-            for (int bp = 0; bp < 8; ++bp) dst[bp] = src[bp * ppL3];
+            for (int c = 0; c < 4; ++c) {
+                const double2 v = src[c];
+                dst[2 * c] = v.x;
+                dst[2 * c + 1] = v.y;
+            }
         };
         fetch(0, cur);
         for (int pi = 0; pi < nP; ++pi) {
@@ -976,9 +982,14 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
         // ring needs no register copies.
         auto fetch = [&](int j, int pi, double *dst) {
             const char4 P = plist[pi];
-            const double *src = S + (int64_t)j * 8 * ppL3 + ((int64_t)P.z * pp + P.y) * pp + P.x;
+            const double2 *src =
+                reinterpret_cast<const double2 *>(S + ((int64_t)j * ppL3 + ((int64_t)P.z * pp + P.y) * pp + P.x) * 8);
 #pragma unroll
-            for (int bp = 0; bp < 8; ++bp) dst[bp] = src[bp * ppL3];
+            for (int c = 0; c < 4; ++c) {
+                const double2 v = src[c];
+                dst[2 * c] = v.x;
+                dst[2 * c + 1] = v.y;
+            }
         };
         int fj = 0, fi = 0;              // plane and entry of the next fetch
         auto fetch_next = [&](double *dst) {    // wraps to the start after the last step
