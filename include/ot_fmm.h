@@ -162,6 +162,12 @@ typedef struct {
 } ot_fmm_timing;
 
 int ot_fmm_timing_begin(ot_fmm_plan plan, int max_calls);
+/* Restrict the events of the calls that follow to the phases whose bit
+ * (1u << phase) is set in phase_mask; timing_begin selects every phase.  Each
+ * recorded phase adds two events to the stream, so timing one phase perturbs
+ * the measured calls least.  Needs an active timing_begin; a mask of 0 or
+ * with bits beyond OT_FMM_NUM_PHASES is INVALID_ARGUMENT. */
+int ot_fmm_timing_phases(ot_fmm_plan plan, uint32_t phase_mask);
 int ot_fmm_timing_end(ot_fmm_plan plan, ot_fmm_timing *out);
 const char *ot_fmm_phase_name(int phase);
 

@@ -528,7 +528,7 @@ struct Phase {
     Phase(ot_fmm_plan P_, hipStream_t s_, int phase_, int launches_) : P(P_), s(s_), phase(phase_), launches(launches_)
     {
         TimingState &T = P->timing;
-        if (!T.active || T.calls >= T.max_calls || T.next + 2 > T.pool.size()) return;
+        if (!T.active || T.calls >= T.max_calls || T.next + 2 > T.pool.size() || !((T.mask >> phase) & 1u)) return;
         a = T.pool[T.next++];
         b = T.pool[T.next++];
         (void)hipEventRecord(a, s);
@@ -742,6 +742,16 @@ int ot_fmm_timing_begin(ot_fmm_plan P, int max_calls)
     }
     T.active = true;
     T.max_calls = max_calls;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_timing_phases(ot_fmm_plan P, uint32_t phase_mask)
+{
+    if (!P) return fail(OT_FMM_INVALID_ARGUMENT, "plan is NULL");
+    if (!P->timing.active) return fail(OT_FMM_INVALID_ARGUMENT, "no active timing_begin");
+    if (phase_mask == 0 || (phase_mask >> OT_FMM_NUM_PHASES) != 0)
+        return fail(OT_FMM_INVALID_ARGUMENT, "phase mask selects no phase or an unknown one");
+    P->timing.mask = phase_mask;
     return OT_FMM_OK;
 }
 

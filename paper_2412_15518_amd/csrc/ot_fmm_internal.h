@@ -95,6 +95,7 @@ struct TimingState {
     bool active = false;
     int max_calls = 0;
     int calls = 0;
+    uint32_t mask = ~0u;               // phases that record events
     std::vector<hipEvent_t> pool;      // pre-created events
     size_t next = 0;
     struct Rec { int phase; int launches; hipEvent_t a, b; };

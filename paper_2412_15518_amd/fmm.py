@@ -34,7 +34,7 @@ PHASES = ["upward_leaf", "m2m", "m2l", "l2l", "leaf", "upward_leaf_adj", "leaf_a
 
 EXPORTS = ["ot_fmm_plan_create", "ot_fmm_forward", "ot_fmm_adjoint", "ot_fmm_plan_info",
            "ot_fmm_destroy", "ot_fmm_status_string", "ot_fmm_last_error", "ot_fmm_timing_begin",
-           "ot_fmm_timing_end", "ot_fmm_phase_name"]
+           "ot_fmm_timing_end", "ot_fmm_phase_name", "ot_fmm_timing_phases"]
 
 
 class OTFMMError(RuntimeError):
@@ -94,6 +94,8 @@ def load_library():
     lib.ot_fmm_timing_end.restype = C.c_int
     lib.ot_fmm_phase_name.argtypes = [C.c_int]
     lib.ot_fmm_phase_name.restype = C.c_char_p
+    lib.ot_fmm_timing_phases.argtypes = [vp, C.c_uint32]
+    lib.ot_fmm_timing_phases.restype = C.c_int
     _lib = lib
     return lib
 
@@ -203,6 +205,13 @@ class Plan:
     # ----------------------------------------------------------------- timing
     def timing_begin(self, max_calls: int):
         _check(load_library().ot_fmm_timing_begin(self._handle, int(max_calls)))
+
+    def timing_phases(self, phases):
+        """Record events only around the named phases (after timing_begin)."""
+        mask = 0
+        for name in phases:
+            mask |= 1 << PHASES.index(name)
+        _check(load_library().ot_fmm_timing_phases(self._handle, C.c_uint32(mask)))
 
     def timing_end(self) -> dict:
         t = _Timing()

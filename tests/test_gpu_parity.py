@@ -308,6 +308,20 @@ def test_timing_api():
     assert t["phases"]["m2l"]["events"] == 4 and t["phases"]["m2l"]["ms"] > 0
     assert t["phases"]["leaf"]["events"] == 3 and t["phases"]["leaf_adj"]["events"] == 1
     assert t["phases"]["total"]["events"] == 4
+    # events restricted to one phase
+    plan.timing_begin(4)
+    plan.timing_phases(["m2l"])
+    plan.forward(r)
+    plan.forward(r)
+    t = plan.timing_end()
+    assert t["calls"] == 2 and t["phases"]["m2l"]["events"] == 2 and t["phases"]["m2l"]["ms"] > 0
+    assert all(v["events"] == 0 for k, v in t["phases"].items() if k != "m2l")
+    with pytest.raises(fmm.OTFMMError):
+        plan.timing_phases(["m2l"])                 # no active timing_begin
+    plan.timing_begin(1)
+    with pytest.raises(fmm.OTFMMError):
+        fmm._check(fmm.load_library().ot_fmm_timing_phases(plan._handle, 0))
+    plan.timing_end()
 
 
 def test_bad_tensor_arguments_raise():
