@@ -53,7 +53,7 @@ extern "C" {
 #define OT_FMM_INVALID_LAYOUT      -2  /* not a proper octree (see plan_create) */
 #define OT_FMM_UNSUPPORTED_ORDER   -3  /* order other than 3 */
 #define OT_FMM_UNSUPPORTED_THETA   -4  /* theta outside (1/3, 1] */
-#define OT_FMM_UNSUPPORTED_LAYOUT  -5  /* valid octree this build cannot run (leaves at several levels, depth > 7) */
+#define OT_FMM_UNSUPPORTED_LAYOUT  -5  /* valid octree this build cannot run (leaves at several levels, depth > 6) */
 #define OT_FMM_OUT_OF_MEMORY       -6  /* host or device allocation failed */
 #define OT_FMM_DEVICE_ERROR        -7  /* a HIP call failed */
 #define OT_FMM_NO_DEVICE_STATE     -8  /* plan created with OT_FMM_HOST_ONLY */

@@ -161,8 +161,8 @@ int validate_layout(const ot_octree_layout *lay, ot_fmm_plan P)
             return fail(OT_FMM_INVALID_LAYOUT, buf);
         }
     }
-    if (L > MAX_LEVELS - 1)
-        return fail(OT_FMM_UNSUPPORTED_LAYOUT, "octree deeper than 7 levels");
+    if (L > MAX_DEPTH)
+        return fail(OT_FMM_UNSUPPORTED_LAYOUT, "octree deeper than 6 levels (more than 512^3 leaf cells)");
     for (int64_t i = 0; i < n; ++i)
         if (lay->is_leaf[i] && lay->level[i] != L)
             return fail(OT_FMM_UNSUPPORTED_LAYOUT,

@@ -29,7 +29,11 @@ constexpr int SUB = 8;                          // cells per sub-grid axis
 constexpr int OFF_R = 7;                        // offset tables span [-7, 7]^3
 constexpr int OFF_W = 2 * OFF_R + 1;
 constexpr int OFF_N = OFF_W * OFF_W * OFF_W;    // 3375
-constexpr int MAX_LEVELS = 8;                   // leaf level L <= 7
+constexpr int MAX_LEVELS = 8;                   // per-level arrays in the plan
+// deepest supported leaf level: the M2L stencil offsets of a level are 32-bit
+// (component x child x padded parent grid, 3.7e8 at the deepest M2L level of
+// depth 6; depth 7 would overflow them)
+constexpr int MAX_DEPTH = 6;
 constexpr int WG = 256;                         // threads per workgroup (4 waves)
 
 __host__ __device__ inline int off_index(int ox, int oy, int oz)

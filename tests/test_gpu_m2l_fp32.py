@@ -120,3 +120,17 @@ def test_fp32_deterministic_bitwise():
     b = plan.forward(r)
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_fp32_depth5_two_spans():
+    """256^3 (depth 5): the upper M2M span also writes the FP32 moments."""
+    n, L = 256, 5
+    rng = np.random.default_rng(730)
+    rho = rng.uniform(0.0, 1.0, (n, n, n))
+    lay = W.uniform_layout(L)
+    say("256^3 fp32 and fp64")
+    a = run(lay, rho=rho, fp32=True)
+    b = run(lay, rho=rho, fp32=False)
+    ep, eg = normwise(a["phi"], b["phi"]), normwise_vec(a["g"], b["g"])
+    say(f"256^3 vs fp64 path: phi {ep:.2e}  g {eg:.2e}")
+    assert ep < TOL32 and eg < TOL32

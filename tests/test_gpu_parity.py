@@ -219,6 +219,19 @@ def test_adjoint_matches_oracle_small(L):
     assert normwise(dr, do) < TOL
 
 
+@pytest.mark.parametrize("order", ["random", "morton"])
+def test_adjoint_other_layout_orders(order):
+    """The adjoint reads and writes the caller's sub-grid order through the
+    same leaf table as the forward."""
+    n = 32
+    rng = np.random.default_rng(330)
+    w = rng.standard_normal((n, n, n))
+    u = rng.standard_normal((3, n, n, n))
+    lay = W.uniform_layout(2, order=order, seed=7)
+    dr = gpu_adjoint(lay, w, u)
+    assert normwise(dr, O.fmm_adjoint(w, u)) < TOL
+
+
 def test_adjoint_cfg5_matches_oracle_and_fd():
     """64^3 lognormal sphere: GPU adjoint == oracle adjoint, and central finite
     differences of L = sum w phi + sum u g through the GPU forward on the 64

@@ -200,6 +200,23 @@ def test_adaptive_layout_is_reported_unsupported():
     assert "several levels" in _expect(fmm.UNSUPPORTED_LAYOUT, bad)
 
 
+def test_too_deep_layout_is_reported_unsupported():
+    """A valid octree reaching level 7 (one refined branch per level): deeper
+    than the 6 levels this build runs."""
+    lv, co, pa, il = [0], [(0, 0, 0)], [-1], [1]
+    node = 0
+    for level in range(1, 8):
+        il[node] = 0
+        first = len(lv)
+        for b in range(8):
+            c = tuple(2 * co[node][k] + ((b >> k) & 1) for k in range(3))
+            lv.append(level); co.append(c); pa.append(node); il.append(1)
+        node = first
+    deep = W.Layout(level=np.array(lv, np.int32), coord=np.array(co, np.int32), parent=np.array(pa, np.int32),
+                    is_leaf=np.array(il, np.uint8))
+    assert "deeper than 6" in _expect(fmm.UNSUPPORTED_LAYOUT, deep)
+
+
 def test_plan_is_independent_of_layout_buffers():
     """plan_create copies what it needs; the caller may free the layout."""
     lay = W.uniform_layout(2, order="random", seed=1)
