@@ -9,9 +9,9 @@
  * the benchmark do.  It shares no code, header, table or constant with the GPU
  * path.
  *
- * The paper names the method but gives none of its formulas; the readings used
- * here (geometric expansion centres, total-order truncation, the parity-aware
- * opening rule) are listed in the design notes of the repository.
+ * The paper names the method but gives none of its formulas; this file reads
+ * it with geometric expansion centres, total-order truncation and the
+ * parity-aware opening rule, all stated below.
  *
  * Geometry (uniform tree of 8^3-cell sub-grids):
  *   level l = 0..L has n_l = 8*2^l cells per axis and cell width h_l = h*2^(L-l);

@@ -14,9 +14,13 @@
 //   P2P   phi_i += K0(o) m_{i+o}, g_i += K1(o) m_{i+o} for every leaf pair whose
 //         parents are near (the far children of near parents included: with
 //         point-mass leaves both evaluations are exact and coincide).
-// The adjoint runs the same pipeline on dual sources: its transpose equals the
-// forward chain applied to a leaf monopole w and scaled dipole u (see the
-// derivation in the design notes); only the leaf stages differ.
+// The adjoint runs the same pipeline on dual sources.  Transposed stage by
+// stage, the forward chain becomes: L2P^T puts a monopole w and a scaled
+// dipole +u at each leaf centre; L2L^T is the scaled M2M; M2L^T is the same
+// M2L kernel, since D^{a+b}(-R) = (-1)^{|a|+|b|} D^{a+b}(R) and the factors
+// (-1)^{|a|}, (-1)^{|b|} are absorbed into the dual variables (which is why
+// the dipole enters as +u); M2M^T is the L2L; P2M^T is the potential-only L2P
+// times h^3.  So only the leaf stages differ.
 //
 // Work mapping: a lane owns one parent cell q of the level and the children
 // 2q + b of it, so every stencil offset o = 2P + b' - b is uniform across a
@@ -343,9 +347,11 @@ __device__ __forceinline__ void span_cell(int ax, int ay, int az, int j, int idx
 // previous step through LDS.
 constexpr int M2M_SPAN_WG = 512;
 
+// four waves per SIMD (at most 128 registers): two 8-wave workgroups per CU,
+// so the 512 workgroups of depth 4 run in one round
 template <int SRC>
-__global__ __launch_bounds__(M2M_SPAN_WG) __attribute__((amdgpu_waves_per_eu(4))) void k_m2m_span(const DevPlan p, const double *__restrict__ a0,
-                                                          const double *__restrict__ a1, int ltop, int nlev)
+__global__ __launch_bounds__(M2M_SPAN_WG) __attribute__((amdgpu_waves_per_eu(4)))
+void k_m2m_span(const DevPlan p, const double *__restrict__ a0, const double *__restrict__ a1, int ltop, int nlev)
 {
     __shared__ double Ms[2][64][NC];      // moments of the span's cells at depths 1 and 2
     const int n = 8 << ltop;
@@ -599,9 +605,11 @@ __device__ __forceinline__ void m2l1f_child(float *C, const float *D, const floa
 constexpr int M2LF_QUADS = M2L_TBP * NC / 4;                  // (child, 4 components) rows per tile
 constexpr int M2LF_QUADS_PER_WAVE = (M2LF_QUADS + 7) / 8;     // at most
 
-__global__ __launch_bounds__(M2L_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32,
-                                                    const char4 *__restrict__ near, const char4 *__restrict__ cube,
-                                                    const M2LDesc *__restrict__ descs)
+// six waves per SIMD, as the FP64 kernel: left alone the compiler takes 100
+// registers and four waves, which is slower
+__global__ __launch_bounds__(M2L_WG) __attribute__((amdgpu_waves_per_eu(6)))
+void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *__restrict__ near,
+               const char4 *__restrict__ cube, const M2LDesc *__restrict__ descs)
 {
     // [buffer][child of the tile][component quad][lane] -> 4 components
     __shared__ float4 tile[2][M2L_TBP][NC / 4][64];
@@ -853,7 +861,8 @@ __device__ __forceinline__ double l2p_phi(const double *C, const double *em, std
 
 // gradient at child B: gr[k] += e_g C[g + e_k], |g| <= 2
 template <int B, int... I>
-__device__ __forceinline__ void l2p_grad(double *gr, const double *C, const double *em, std::integer_sequence<int, I...>)
+__device__ __forceinline__ void l2p_grad(double *gr, const double *C, const double *em,
+                                         std::integer_sequence<int, I...>)
 {
     constexpr Terms<30> T = make_grad_terms();
     ((gr[T.t[I].i] = fma(neg_of(B, T.t[I].j) ? -em[T.t[I].j] : em[T.t[I].j], C[T.t[I].k], gr[T.t[I].i])), ...);
