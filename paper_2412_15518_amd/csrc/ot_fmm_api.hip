@@ -501,9 +501,20 @@ int setup_device(ot_fmm_plan P)
         v.nbx = v.np / v.bx;
         v.nby = v.np / v.by;
         const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;
-        if ((rc = dev_alloc(P, &v.M, (size_t)NC * 8 * pp3, true))) return rc;
+        // full moments where an M2M launch reads them back from memory: the
+        // top level of every span below another span, and level L-1 for the
+        // adjoint's bottom span (the forward forms level L-1 inside it)
+        bool full = (l == L - 1 && d.n_span > 0);
+        for (int i = 1; i < d.n_span; ++i) full = full || (l == d.span_top[i]);
+        v.M = nullptr;
+        v.Mr = nullptr;
         v.M32 = nullptr;
-        if (d.m2l_fp32 && (rc = dev_alloc(P, &v.M32, (size_t)NC * 8 * pp3, true))) return rc;
+        if (full && (rc = dev_alloc(P, &v.M, (size_t)NC * 8 * pp3, true))) return rc;
+        if (d.m2l_fp32) {
+            if ((rc = dev_alloc(P, &v.M32, (size_t)NR * 8 * pp3, true))) return rc;
+        } else if ((rc = dev_alloc(P, &v.Mr, (size_t)NR * 8 * pp3, true))) {
+            return rc;
+        }
         if (l < L - 1 && (rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;

@@ -4,8 +4,12 @@
 //   A cell c of level l is addressed through its parent q = c >> 1 and its
 //   child index b = (c_x & 1) + 2 (c_y & 1) + 4 (c_z & 1).  Every level below
 //   the leaves keeps
-//     M[l] : scaled moments   [NC][8][pp^3]  over the parent grid padded by a
-//            zero halo of hp parents per side (pp = np + 2 hp, np = n_l / 2),
+//     Mr[l]: the M2L's reduced moments over the parent grid padded by a zero
+//            halo of hp parents per side (pp = np + 2 hp, np = n_l / 2), in
+//            groups of one 16-byte load: [NR/2][8][pp^3][2]; FP32 in M32[l]
+//            ([NR/4][8][pp^3][4]) when the M2L runs in FP32,
+//     M[l] : the full scaled moments [NC][8][pp^3], only at the levels an M2M
+//            launch reads back from memory,
 //     C[l] : local coefficients [NC][8][np^3]  (levels below L-1; the leaf
 //            pass forms the locals of level L-1 in registers),
 //   so the 64 lanes of a wave that handle 64 neighbouring parents read
@@ -25,6 +29,7 @@
 namespace otfmm {
 
 constexpr int NC = 20;                          // components of orders 0..3
+constexpr int NR = 16;                          // components of the reduced M2L form (z-power <= 1)
 constexpr int SUB = 8;                          // cells per sub-grid axis
 constexpr int OFF_R = 7;                        // offset tables span [-7, 7]^3
 constexpr int OFF_W = 2 * OFF_R + 1;
@@ -49,8 +54,9 @@ struct DevLevel {
     int bx, by, bz;  // M2L block shape (64 parents)
     int nbx, nby;    // blocks per axis in x and y
     double h;        // cell width of this level
-    double *M;       // [NC][8][pp^3]
-    float *M32;      // FP32 copy of M for the FP32 M2L (null unless the plan asks for it)
+    double *M;       // [NC][8][pp^3] full moments; null unless an M2M reads this level from memory
+    double *Mr;      // [NR/2][8][pp^3][2] reduced moments, M2L sources (FP64 M2L; else null)
+    float *M32;      // [NR/4][8][pp^3][4] the same in FP32 (FP32 M2L; else null)
     double *C;       // [NC][8][np^3] local coefficients (final); null at level L-1
     double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
 };

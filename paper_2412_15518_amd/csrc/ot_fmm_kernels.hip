@@ -8,7 +8,8 @@
 //   e_a(x) = x^a / a!  (component order below)
 //   M2M   Mt_P^a += sum_{b <= a} e_{a-b}(z_P - z_c) Mt_c^b
 //   M2L   C_A^a  += sum_{|a|+|b| <= 3} D^{a+b}(z_A - z_B) Mt_B^b,
-//         D = derivative tensor of K(r) = -G/|r|
+//         D = derivative tensor of K(r) = -G/|r|, evaluated in the reduced
+//         form below (16 source and 16 sink components, 70 FMA per pair)
 //   L2L   C_c^a  += sum_{|a|+|g| <= 3} e_g(z_c - z_P) C_P^{a+g}
 //   L2P   phi = C^0, g = -C^{e_k} at the leaf centre
 //   P2P   phi_i += K0(o) m_{i+o}, g_i += K1(o) m_{i+o} for every leaf pair whose
@@ -114,41 +115,143 @@ static_assert(make_sub_terms().n == 84, "84 shift terms");
 static_assert(make_dipole_terms().n == 30, "30 dipole terms");
 static_assert(make_grad_terms().n == 30, "30 gradient terms");
 
-// the same 84 terms ordered by source component b: every M[b] is consumed
-// right after it is read, by all sinks at once
-constexpr Terms<84> make_sum_terms_by_source()
+// ------------------------------------------------------------------------
+// Reduced form of the M2L.  K = -G/r is harmonic away from the origin, so its
+// derivative tensors are traceless: D^{c+2x} + D^{c+2y} + D^{c+2z} = 0 for
+// every c.  A component k with a z-power of 2 or more (zz, xzz, yzz, zzz) is
+// then D^k = -D^{k-2z+2x} - D^{k-2z+2y}, two components of lower z-power.
+// Substituting this on both sides of the contraction gives:
+//   sources: sum_b D^{a+b} Mt^b = sum over the 16 kept b of D^{a+b} R^b with
+//            R^c = Mt^c - Mt^{c-2x+2z} [c_x >= 2] - Mt^{c-2y+2z} [c_y >= 2]
+//            (formed once per cell when its moments are stored);
+//   sinks:   the M2L's share of C^k for the 4 dropped k follows from the kept
+//            ones, C^k = -C^{k-2z+2x} - C^{k-2z+2y} (formed once per stored
+//            partial sum).
+// Kept are the 16 components with z-power <= 1, in the order of kMI.  A pair
+// costs 70 FMA over 16 source values instead of 84 over 20; the operator is
+// the same up to rounding.
+// ------------------------------------------------------------------------
+struct RedTab {
+    int full[NR];                  // kept component r -> its index in kMI
+    int red_of[NC];                // index in kMI -> kept component, or -1
+    int sub1[NR], sub2[NR];        // R^r = Mt^full - Mt^sub1 - Mt^sub2 (-1: no term)
+    int dep1[NC], dep2[NC];        // dropped k: C^k = -C^dep1 - C^dep2 (kept indices)
+};
+constexpr RedTab make_red()
 {
-    Terms<84> T{};
+    RedTab R{};
+    int n = 0;
+    for (int k = 0; k < NC; ++k) {
+        R.red_of[k] = -1;
+        if (kMI[k].v < 2) {
+            R.full[n] = k;
+            R.red_of[k] = n++;
+        }
+    }
+    for (int r = 0; r < NR; ++r) {
+        const MIdx c = kMI[R.full[r]];
+        R.sub1[r] = c.t >= 2 ? comp_of(c.t - 2, c.u, c.v + 2) : -1;
+        R.sub2[r] = c.u >= 2 ? comp_of(c.t, c.u - 2, c.v + 2) : -1;
+    }
+    for (int k = 0; k < NC; ++k) {
+        const MIdx c = kMI[k];
+        R.dep1[k] = c.v >= 2 ? R.red_of[comp_of(c.t + 2, c.u, c.v - 2)] : -1;
+        R.dep2[k] = c.v >= 2 ? R.red_of[comp_of(c.t, c.u + 2, c.v - 2)] : -1;
+    }
+    return R;
+}
+constexpr bool red_ok()
+{
+    const RedTab R = make_red();
+    int n = 0;
+    for (int k = 0; k < NC; ++k) n += R.red_of[k] >= 0;
+    for (int k = 0; k < NC; ++k)
+        if (R.red_of[k] < 0 && (R.dep1[k] < 0 || R.dep2[k] < 0)) return false;
+    return n == NR;
+}
+static_assert(red_ok(), "16 kept components; every dropped one has its two kept partners");
+
+// (a, b, a+b) over kept a, b with |a| + |b| <= 3, ordered by source b: every
+// R[b] is consumed right after it is read, by all sinks at once.  The D index
+// a+b is in kMI order (the derivative rows keep all 20 components).
+constexpr Terms<70> make_red_terms_by_source()
+{
+    const RedTab R = make_red();
+    Terms<70> T{};
     T.n = 0;
-    for (int b = 0; b < NC; ++b)
-        for (int a = 0; a < NC; ++a)
-            if (order_of(a) + order_of(b) <= 3)
-                T.t[T.n++] = {a, b, comp_of(kMI[a].t + kMI[b].t, kMI[a].u + kMI[b].u, kMI[a].v + kMI[b].v)};
+    for (int b = 0; b < NR; ++b)
+        for (int a = 0; a < NR; ++a) {
+            const MIdx x = kMI[R.full[a]], y = kMI[R.full[b]];
+            if (x.t + x.u + x.v + y.t + y.u + y.v <= 3) T.t[T.n++] = {a, b, comp_of(x.t + y.t, x.u + y.u, x.v + y.v)};
+        }
     return T;
 }
-static_assert(make_sum_terms_by_source().n == 84, "84 terms");
+static_assert(make_red_terms_by_source().n == 70, "70 terms of the reduced M2L");
 
-// first term of each source component in the source-major list
+constexpr int terms_of_source(int b)      // b: kept component
+{
+    const int o = order_of(make_red().full[b]);
+    return (o == 0) ? 16 : (o == 1) ? 9 : (o == 2) ? 4 : 1;
+}
 constexpr int source_begin(int b)
 {
     int n = 0;
-    for (int j = 0; j < b; ++j) n += (order_of(j) == 0) ? 20 : (order_of(j) == 1) ? 10 : (order_of(j) == 2) ? 4 : 1;
+    for (int j = 0; j < b; ++j) n += terms_of_source(j);
     return n;
 }
-static_assert(source_begin(NC) == 84, "source-major term ranges");
+static_assert(source_begin(NR) == 70, "source-major term ranges");
 
-// one sink:  C[a] += D[a+b] m  for the terms of source component b
+// one sink:  C[a] += D[a+b] m  for the terms of kept source component b
 template <int B, int... I>
 __device__ __forceinline__ void m2l1_component(double *C, const double *D, double m, std::integer_sequence<int, I...>)
 {
-    constexpr Terms<84> T = make_sum_terms_by_source();
+    constexpr Terms<70> T = make_red_terms_by_source();
     constexpr int o = source_begin(B);
     ((C[T.t[o + I].i] = fma(D[T.t[o + I].k], m, C[T.t[o + I].i])), ...);
 }
 
-constexpr int terms_of_source(int b)
+template <int K>
+__device__ __forceinline__ double comp_or_zero(const double *M)
 {
-    return (order_of(b) == 0) ? 20 : (order_of(b) == 1) ? 10 : (order_of(b) == 2) ? 4 : 1;
+    if constexpr (K >= 0) return M[K];
+    else return 0.0;
+}
+
+// reduced component R of the full scaled moments M
+template <int R>
+__device__ __forceinline__ double reduced(const double *M)
+{
+    constexpr RedTab T = make_red();
+    return M[T.full[R]] - comp_or_zero<T.sub1[R]>(M) - comp_or_zero<T.sub2[R]>(M);
+}
+// The reduced moments are stored in groups of one 16-byte load: FP64 pairs
+// [NR/2][8][pp^3] double2, FP32 quads [NR/4][8][pp^3] float4; out points at
+// the cell's group 0, groups are cs apart.
+template <int... G>
+__device__ __forceinline__ void store_reduced(double2 *out, int64_t cs, const double *M, std::integer_sequence<int, G...>)
+{
+    ((out[G * cs] = make_double2(reduced<2 * G>(M), reduced<2 * G + 1>(M))), ...);
+}
+template <int... G>
+__device__ __forceinline__ void store_reduced(float4 *out, int64_t cs, const double *M, std::integer_sequence<int, G...>)
+{
+    ((out[G * cs] = make_float4((float)reduced<4 * G>(M), (float)reduced<4 * G + 1>(M), (float)reduced<4 * G + 2>(M),
+                                (float)reduced<4 * G + 3>(M))),
+     ...);
+}
+
+// the 20 local coefficients of an M2L sum from its 16 kept ones
+template <int K>
+__device__ __forceinline__ double expand_one(const double *Cr)
+{
+    constexpr RedTab T = make_red();
+    if constexpr (T.red_of[K] >= 0) return Cr[T.red_of[K]];
+    else return -(Cr[T.dep1[K]] + Cr[T.dep2[K]]);
+}
+template <int... K>
+__device__ __forceinline__ void expand_locals(double *Cf, const double *Cr, std::integer_sequence<int, K...>)
+{
+    ((Cf[K] = expand_one<K>(Cr)), ...);
 }
 
 // Cc[a] += e[g] Cp[a+g]
@@ -270,20 +373,23 @@ __device__ __forceinline__ void leaf_p2m(const DevPlan &p, const double *__restr
     }
 }
 
-// store the moments of cell c of level l (kept under its parent c >> 1),
-// and their FP32 copy when the FP32 M2L needs one
-__device__ __forceinline__ void store_moments(const DevLevel &D, int cx, int cy, int cz, const double *Mq)
+// store the moments of cell c of level l (kept under its parent c >> 1):
+// always the reduced form the M2L reads (FP64, or FP32 for the FP32 M2L),
+// and the full moments when an M2M launch reads this level back (full)
+__device__ __forceinline__ void store_moments(const DevLevel &D, int cx, int cy, int cz, const double *Mq, bool full)
 {
     const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
     const int64_t pp = D.pp, pp3 = pp * pp * pp;
     const int64_t pad = ((int64_t)((cz >> 1) + D.hp) * pp + ((cy >> 1) + D.hp)) * pp + ((cx >> 1) + D.hp);
     const int64_t at = (int64_t)bs * pp3 + pad, cs = 8 * pp3;
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < NC; ++k) D.M[at + k * cs] = Mq[k];
-    if (D.M32) {
-#pragma unroll
-        for (int k = 0; k < NC; ++k) D.M32[at + k * cs] = (float)Mq[k];
+        for (int k = 0; k < NC; ++k) D.M[at + k * cs] = Mq[k];
     }
+    if (D.M32)
+        store_reduced(reinterpret_cast<float4 *>(D.M32) + at, cs, Mq, std::make_integer_sequence<int, NR / 4>{});
+    else
+        store_reduced(reinterpret_cast<double2 *>(D.Mr) + at, cs, Mq, std::make_integer_sequence<int, NR / 2>{});
 }
 
 // P2M + M2M into level L-1 when no level lies between it and the root
@@ -299,10 +405,16 @@ __global__ __launch_bounds__(WG) void k_upward_leaf(const DevPlan p, const doubl
     const int Qx = (int)(t % npL), Qy = (int)((t / npL) % npL), Qz = (int)(t / ((int64_t)npL * npL));
     double Mq[NC];
     leaf_p2m<ADJ>(p, a0, a1, Qx, Qy, Qz, Mq);
-    if (p.L >= 1) store_moments(p.lev[p.L - 1], Qx, Qy, Qz, Mq);
+    if (p.L >= 1) store_moments(p.lev[p.L - 1], Qx, Qy, Qz, Mq, p.lev[p.L - 1].M != nullptr);
 }
 
 typedef __attribute__((address_space(1))) double gdouble;   // global memory
+typedef __attribute__((address_space(1))) void gvoid;
+typedef __attribute__((address_space(3))) void lvoid;       // LDS
+// s_waitcnt immediate of gfx9 that waits for vmcnt = 0 only (expcnt and
+// lgkmcnt at their maxima): the vector memory operations of this wave,
+// loads into LDS included, are complete
+constexpr int WAIT_VMCNT0 = 0x0F70;
 
 // C[k] += sum over the pieces of cp[(piece * NC + k) * cs]; all loads of a
 // piece are issued before the first add
@@ -373,7 +485,7 @@ void k_m2m_span(const DevPlan p, const double *__restrict__ a0, const double *__
                 // the child is a leaf parent: P2M from its leaf masses, stored for the M2L
                 const int Qx = 2 * cx + (b & 1), Qy = 2 * cy + ((b >> 1) & 1), Qz = 2 * cz + (b >> 2);
                 leaf_p2m<false>(p, a0, a1, Qx, Qy, Qz, Mc);
-                store_moments(p.lev[lv + 1], Qx, Qy, Qz, Mc);
+                store_moments(p.lev[lv + 1], Qx, Qy, Qz, Mc, false);
             } else if (j == nlev - 1) {
                 // the children of c are stored under c in level lv + 1
                 const DevLevel &Dc = p.lev[lv + 1];
@@ -403,7 +515,7 @@ void k_m2m_span(const DevPlan p, const double *__restrict__ a0, const double *__
 #pragma unroll
                 for (int k = 0; k < NC; ++k) Ms[j & 1][ci][k] = Mp[k];
             }
-            store_moments(p.lev[lv], cx, cy, cz, Mp);
+            store_moments(p.lev[lv], cx, cy, cz, Mp, p.lev[lv].M != nullptr);   // full: read by the span above
         }
         __syncthreads();
     }
@@ -413,23 +525,22 @@ void k_m2m_span(const DevPlan p, const double *__restrict__ a0, const double *__
 // M2L
 // ------------------------------------------------------------------------
 constexpr int M2L_TBP = 2;                       // source children per tile
-constexpr int M2L_TILE = M2L_TBP * NC;           // (child, component) rows per tile
 
 // M2L over every level below the leaves in one launch.
 //
 // Exactly one workgroup (8 waves) per resident slot; workgroup g walks its
 // run of units (block, P) of one level in order, 8 / M2L_TBP tiles of M2L_TBP
-// source children per unit.  Wave w handles sink child b = w of its lane's parent,
-// so a lane keeps 20 accumulators and a wave one derivative row (20
-// scalars): few registers, many waves per SIMD to hide the scalar and
-// memory latencies.  The tile of source moments (2 children x 20 components
-// x 64 parents) is loaded once per workgroup -- thread t fetches M2L_TILE/8 of
-// its rows -- and shared through LDS, double-buffered: tile k+1 travels through
-// registers while tile k is consumed, two components per 16-byte LDS read.
-// Sums stay in registers while the block is the same and are stored as a
-// partial sum (piece) when it changes.
+// source children per unit.  Wave w handles sink child b = w of its lane's
+// parent, so a lane keeps 16 accumulators (the reduced form) and a wave one
+// derivative row (20 scalars): few registers, eight waves per SIMD to hide
+// the scalar and LDS latencies.  The tile of reduced source moments (2
+// children x 16 components x 64 parents) is loaded once per workgroup,
+// straight from global memory into LDS (16 bytes per lane, no registers),
+// and read two components per 16-byte LDS read.  It is double-buffered:
+// tile k+1 is in flight while tile k is consumed.  Sums stay in registers
+// while the block is the same and are stored as a partial sum (piece) when
+// it changes.
 constexpr int M2L_WG = 512;                       // 8 waves, one per sink child
-constexpr int M2L_ROWS_PER_THREAD = M2L_TILE * 64 / M2L_WG;   // rows each thread stages
 
 template <int PAIR, int... I>
 __device__ __forceinline__ void m2l1_pair(double *C, const double *D, double2 m, std::integer_sequence<int, I...>)
@@ -438,20 +549,40 @@ __device__ __forceinline__ void m2l1_pair(double *C, const double *D, double2 m,
     m2l1_component<2 * PAIR + 1>(C, D, m.y, std::make_integer_sequence<int, terms_of_source(2 * PAIR + 1)>{});
 }
 
-template <int... PAIR>
-__device__ __forceinline__ void m2l1_child(double *C, const double *D, const double2 *rows, int lane,
-                                           std::integer_sequence<int, PAIR...>)
+// one source child of a tile: rows[pair * 64 + lane] = components
+// (2 pair, 2 pair + 1) of the lane's source.  Six LDS reads go out before the
+// first product (one wait covers them and the derivative row), the last two
+// while the first three component pairs are being consumed: a wave has only
+// two waits per pair, and at most six reads (24 registers) in flight.
+__device__ __forceinline__ void m2l1_child(double *C, const double *D, const double2 *rows, int lane)
 {
-    // rows[pair * 64 + lane] = components (2 pair, 2 pair + 1) of the lane's source
-    (m2l1_pair<PAIR>(C, D, rows[PAIR * 64 + lane], std::integer_sequence<int>{}), ...);
+    static_assert(NR / 2 == 8, "eight component pairs");
+    constexpr std::integer_sequence<int> none{};
+    const double2 m0 = rows[0 * 64 + lane], m1 = rows[1 * 64 + lane], m2 = rows[2 * 64 + lane];
+    const double2 m3 = rows[3 * 64 + lane], m4 = rows[4 * 64 + lane], m5 = rows[5 * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
+    m2l1_pair<0>(C, D, m0, none);
+    m2l1_pair<1>(C, D, m1, none);
+    m2l1_pair<2>(C, D, m2, none);
+    __builtin_amdgcn_sched_barrier(0);
+    const double2 m6 = rows[6 * 64 + lane], m7 = rows[7 * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
+    m2l1_pair<3>(C, D, m3, none);
+    m2l1_pair<4>(C, D, m4, none);
+    m2l1_pair<5>(C, D, m5, none);
+    __builtin_amdgcn_sched_barrier(0);
+    m2l1_pair<6>(C, D, m6, none);
+    m2l1_pair<7>(C, D, m7, none);
 }
 
-__global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *__restrict__ Dtab,
-                                                const char4 *__restrict__ near, const char4 *__restrict__ cube,
-                                                const M2LDesc *__restrict__ descs)
+__global__ __launch_bounds__(M2L_WG) __attribute__((amdgpu_waves_per_eu(8)))
+void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__restrict__ near,
+           const char4 *__restrict__ cube, const M2LDesc *__restrict__ descs)
 {
-    // [buffer][child of the tile][component pair][lane] -> 2 components
-    __shared__ double2 tile[2][M2L_TBP][NC / 2][64];
+    // two tile buffers [child of the tile][component pair][lane] -> 2 components,
+    // separate arrays so that reads of one and loads into the other are
+    // visibly independent
+    __shared__ double2 tile0[M2L_TBP][NR / 2][64], tile1[M2L_TBP][NR / 2][64];
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= p.n_mdesc) return;
     const M2LDesc d = descs[g];
@@ -463,6 +594,7 @@ __global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *_
     const int nP = lev == 0 ? p.n_plist_cube : p.n_plist_near;
     const char4 *__restrict__ plist = lev == 0 ? cube : near;
     const double *__restrict__ Dl = Dtab + (size_t)lev * OFF_N * NC;
+    const double2 *__restrict__ Mr = reinterpret_cast<const double2 *>(D.Mr);
     const int np = D.np, pp = D.pp, hp = D.hp;
     const int pp3 = pp * pp * pp, np3 = np * np * np;
     const int lx = lane & (D.bx - 1), ly = (lane / D.bx) & (D.by - 1), lz = lane / (D.bx * D.by);
@@ -482,55 +614,47 @@ __global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *_
         return ((qz + hp) * pp + (qy + hp)) * pp + (qx + hp);
     };
     constexpr int TPP = 8 / M2L_TBP;                // tiles per unit
-    static_assert(M2L_TILE % 8 == 0, "each wave stages the same number of rows");
+    constexpr int ROWS = M2L_TBP * NR / 2;          // 16-byte rows of 64 lanes per tile
+    static_assert(ROWS % 8 == 0, "each wave loads the same number of rows");
     const int ntiles = (d.uend - d.ubeg) * TPP;
 
-    // fetch cursor: block fb, parent offset fi, tile ft.  Thread (wave w, lane)
-    // stages rows r = w + 8 j: component r % 20 of tile child r / 20
+    // fetch cursor: block fb, parent offset fi, tile ft.  Wave w loads rows
+    // r = w + 8 j of the next tile (component pair r % 8 of tile child r / 8)
+    // straight from global memory into LDS, 16 bytes per lane.
     int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
     int fmq = lane_mq(fb);
-    auto fetch = [&](double *reg) {
+    auto fetch = [&](double2 (*t)[NR / 2][64]) {
         const char4 P = plist[fi];
-        const double *src = D.M + (fmq + ft * M2L_TBP * pp3 + (P.z * pp + P.y) * pp + P.x);
+        const double2 *src = Mr + (fmq + ft * M2L_TBP * pp3 + (P.z * pp + P.y) * pp + P.x);
 #pragma unroll
-        for (int j = 0; j < M2L_ROWS_PER_THREAD; ++j) {
-            const int r = b + 8 * j;
-            int off = ((r % NC) * 8 + r / NC) * pp3;
-            asm volatile("" : "+s"(off));       // recomputed per tile: hoisted, five would pin registers
-            reg[j] = src[off];
+        for (int j = 0; j < ROWS / 8; ++j) {
+            const int r = b + 8 * j, i = r / (NR / 2), k = r % (NR / 2);
+            __builtin_amdgcn_global_load_lds((gvoid *)(src + (k * 8 + i) * pp3), (lvoid *)&t[i][k][0], 16, 0, 0);
         }
     };
-    auto stash = [&](int buf, const double *reg) {
-        double *t = reinterpret_cast<double *>(&tile[buf][0][0][0]);
-#pragma unroll
-        for (int j = 0; j < M2L_ROWS_PER_THREAD; ++j) {
-            const int r = b + 8 * j, i = r / NC, k = r % NC;
-            t[((i * (NC / 2) + (k >> 1)) * 64 + lane) * 2 + (k & 1)] = reg[j];
-        }
-    };
+    // the loads of this wave have reached LDS; with the barrier after it,
+    // those of every wave
+    auto loads_done = [&]() { __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0); };
 
     // compute cursor
     int cb = fb, ci = fi, ct = 0;
     int piece = d.piece0;
 
-    double C[NC];
+    double C[NR];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) C[k] = 0.0;
+    for (int k = 0; k < NR; ++k) C[k] = 0.0;
     auto flush = [&]() {
         double *out = D.Cp + (size_t)piece * NC * 8 * np3 + lane_q(cb);
+        double Cf[NC];
+        expand_locals(Cf, C, std::make_integer_sequence<int, NC>{});
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            out[(size_t)(k * 8 + b) * np3] = C[k];
-            C[k] = 0.0;
-        }
+        for (int k = 0; k < NC; ++k) out[(size_t)(k * 8 + b) * np3] = Cf[k];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) C[k] = 0.0;
     };
 
-    double reg[M2L_ROWS_PER_THREAD];
-    fetch(reg);
-    stash(0, reg);
-    __syncthreads();
-
-    for (int k = 0; k < ntiles; ++k) {
+    // one tile: start loading the next one into nxt, consume cur
+    auto step = [&](int k, double2 (*cur)[NR / 2][64], double2 (*nxt)[NR / 2][64]) {
         if (k + 1 < ntiles) {
             if (++ft == TPP) {
                 ft = 0;
@@ -539,9 +663,8 @@ __global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *_
                     fmq = lane_mq(++fb);
                 }
             }
-            fetch(reg);
+            fetch(nxt);
         }
-        const int buf = k & 1;
         const char4 P = plist[ci];
         const int bp0 = ct * M2L_TBP;
 #pragma unroll
@@ -554,7 +677,7 @@ __global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *_
             double Dv[NC];
 #pragma unroll
             for (int q = 0; q < NC; ++q) Dv[q] = Dr[q];
-            m2l1_child(C, Dv, &tile[buf][i][0][0], lane, std::make_integer_sequence<int, NC / 2>{});
+            m2l1_child(C, Dv, &cur[i][0][0], lane);
         }
         if (++ct == TPP) {
             ct = 0;
@@ -565,22 +688,30 @@ __global__ __launch_bounds__(M2L_WG) void k_m2l(const DevPlan p, const double *_
                 ++cb;
             }
         }
-        if (k + 1 < ntiles) stash(buf ^ 1, reg);
+        loads_done();
         __syncthreads();
+    };
+
+    fetch(tile0);
+    loads_done();
+    __syncthreads();
+    for (int k = 0; k < ntiles; k += 2) {
+        step(k, tile0, tile1);
+        if (k + 1 < ntiles) step(k + 1, tile1, tile0);
     }
     if (ci != 0 || ct != 0) flush();            // run ended inside a block
 }
 
 // M2L in FP32 (plan flag OT_FMM_M2L_FP32).  The schedule, the work mapping
 // and the partial sums are those of k_m2l; the moments and derivative rows
-// are FP32, the LDS tile holds four components per 16-byte read, and the 84
+// are FP32, the LDS tile holds four components per 16-byte read, and the 70
 // products of a pair are accumulated in FP32 over one parent offset (the 8
 // source children of a unit) and then added to FP64 accumulators, which the
 // pieces receive.
 template <int B, int... I>
 __device__ __forceinline__ void m2l1f_component(float *C, const float *D, float m, std::integer_sequence<int, I...>)
 {
-    constexpr Terms<84> T = make_sum_terms_by_source();
+    constexpr Terms<70> T = make_red_terms_by_source();
     constexpr int o = source_begin(B);
     ((C[T.t[o + I].i] = fmaf(D[T.t[o + I].k], m, C[T.t[o + I].i])), ...);
 }
@@ -602,17 +733,19 @@ __device__ __forceinline__ void m2l1f_child(float *C, const float *D, const floa
     (m2l1f_quad<Q>(C, D, rows[Q * 64 + lane]), ...);
 }
 
-constexpr int M2LF_QUADS = M2L_TBP * NC / 4;                  // (child, 4 components) rows per tile
-constexpr int M2LF_QUADS_PER_WAVE = (M2LF_QUADS + 7) / 8;     // at most
+constexpr int M2LF_QUADS = M2L_TBP * NR / 4;                  // (child, 4 components) rows per tile
+static_assert(M2LF_QUADS == 8, "one quad row per wave");
 
-// six waves per SIMD, as the FP64 kernel: left alone the compiler takes 100
-// registers and four waves, which is slower
+// one quad row (16 bytes per lane) per wave and tile
+static_assert(M2L_TBP * NR / 4 == 8, "one quad row per wave");
+
+// six waves per SIMD (at most 80 registers); eight would spill
 __global__ __launch_bounds__(M2L_WG) __attribute__((amdgpu_waves_per_eu(6)))
 void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *__restrict__ near,
                const char4 *__restrict__ cube, const M2LDesc *__restrict__ descs)
 {
-    // [buffer][child of the tile][component quad][lane] -> 4 components
-    __shared__ float4 tile[2][M2L_TBP][NC / 4][64];
+    // two tile buffers [child of the tile][component quad][lane] -> 4 components
+    __shared__ float4 tile0[M2L_TBP][NR / 4][64], tile1[M2L_TBP][NR / 4][64];
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= p.n_mdesc) return;
     const M2LDesc d = descs[g];
@@ -624,6 +757,7 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
     const int nP = lev == 0 ? p.n_plist_cube : p.n_plist_near;
     const char4 *__restrict__ plist = lev == 0 ? cube : near;
     const float *__restrict__ Dl = Dtab32 + (size_t)lev * OFF_N * NC;
+    const float4 *__restrict__ M32 = reinterpret_cast<const float4 *>(D.M32);
     const int np = D.np, pp = D.pp, hp = D.hp;
     const int pp3 = pp * pp * pp, np3 = np * np * np;
     const int lx = lane & (D.bx - 1), ly = (lane / D.bx) & (D.by - 1), lz = lane / (D.bx * D.by);
@@ -645,46 +779,31 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
     constexpr int TPP = 8 / M2L_TBP;                // tiles per unit
     const int ntiles = (d.uend - d.ubeg) * TPP;
 
-    // fetch cursor as in k_m2l; wave w stages quad rows r = w + 8 u (child
-    // r / 5, components 4 (r % 5) .. + 3) of its lane's source, one 16-byte
-    // LDS write each
+    // fetch cursor as in k_m2l; wave w loads quad row w of the next tile
+    // (tile child w / 4, reduced components 4 (w % 4) .. + 3) into LDS
     int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
     int fmq = lane_mq(fb);
-    auto fetch = [&](float *reg) {
+    const int ti = b / (NR / 4), tq = b % (NR / 4);
+    auto fetch = [&](float4 (*t)[NR / 4][64]) {
         const char4 P = plist[fi];
-        const float *src = D.M32 + (fmq + ft * M2L_TBP * pp3 + (P.z * pp + P.y) * pp + P.x);
-#pragma unroll
-        for (int u = 0; u < M2LF_QUADS_PER_WAVE; ++u) {
-            const int r = b + 8 * u;
-            const int off = ((4 * (r % 5)) * 8 + r / 5) * pp3;
-            if (r < M2LF_QUADS) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) reg[4 * u + c] = src[off + c * 8 * pp3];
-            }
-        }
+        const float4 *src = M32 + (fmq + ft * M2L_TBP * pp3 + (P.z * pp + P.y) * pp + P.x);
+        __builtin_amdgcn_global_load_lds((gvoid *)(src + (tq * 8 + ti) * pp3), (lvoid *)&t[ti][tq][0], 16, 0, 0);
     };
-    auto stash = [&](int buf, const float *reg) {
-#pragma unroll
-        for (int u = 0; u < M2LF_QUADS_PER_WAVE; ++u) {
-            const int r = b + 8 * u;
-            if (r < M2LF_QUADS)
-                tile[buf][r / 5][r % 5][lane] = make_float4(reg[4 * u], reg[4 * u + 1], reg[4 * u + 2], reg[4 * u + 3]);
-        }
-    };
+    auto loads_done = [&]() { __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0); };
 
     int cb = fb, ci = fi, ct = 0;
     int piece = d.piece0;
 
-    double C[NC];           // FP64 accumulators of the block
-    float Cf[NC];           // FP32 sum of the current parent offset
+    double C[NR];           // FP64 accumulators of the block
+    float Cf[NR];           // FP32 sum of the current parent offset
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
+    for (int k = 0; k < NR; ++k) {
         C[k] = 0.0;
         Cf[k] = 0.0f;
     }
     auto fold = [&]() {
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
+        for (int k = 0; k < NR; ++k) {
             C[k] += (double)Cf[k];
             Cf[k] = 0.0f;
         }
@@ -692,19 +811,15 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
     auto flush = [&]() {
         fold();
         double *out = D.Cp + (size_t)piece * NC * 8 * np3 + lane_q(cb);
+        double Cx[NC];
+        expand_locals(Cx, C, std::make_integer_sequence<int, NC>{});
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            out[(size_t)(k * 8 + b) * np3] = C[k];
-            C[k] = 0.0;
-        }
+        for (int k = 0; k < NC; ++k) out[(size_t)(k * 8 + b) * np3] = Cx[k];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) C[k] = 0.0;
     };
 
-    float reg[4 * M2LF_QUADS_PER_WAVE];
-    fetch(reg);
-    stash(0, reg);
-    __syncthreads();
-
-    for (int k = 0; k < ntiles; ++k) {
+    auto step = [&](int k, float4 (*cur)[NR / 4][64], float4 (*nxt)[NR / 4][64]) {
         if (k + 1 < ntiles) {
             if (++ft == TPP) {
                 ft = 0;
@@ -713,9 +828,8 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
                     fmq = lane_mq(++fb);
                 }
             }
-            fetch(reg);
+            fetch(nxt);
         }
-        const int buf = k & 1;
         const char4 P = plist[ci];
         const int bp0 = ct * M2L_TBP;
 #pragma unroll
@@ -728,7 +842,7 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
             float Dv[NC];
 #pragma unroll
             for (int q = 0; q < NC; ++q) Dv[q] = Dr[q];
-            m2l1f_child(Cf, Dv, &tile[buf][i][0][0], lane, std::make_integer_sequence<int, NC / 4>{});
+            m2l1f_child(Cf, Dv, &cur[i][0][0], lane, std::make_integer_sequence<int, NR / 4>{});
         }
         if (++ct == TPP) {
             ct = 0;
@@ -740,8 +854,16 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
                 ++cb;
             }
         }
-        if (k + 1 < ntiles) stash(buf ^ 1, reg);
+        loads_done();
         __syncthreads();
+    };
+
+    fetch(tile0);
+    loads_done();
+    __syncthreads();
+    for (int k = 0; k < ntiles; k += 2) {
+        step(k, tile0, tile1);
+        if (k + 1 < ntiles) step(k + 1, tile1, tile0);
     }
     if (ci != 0 || ct != 0) flush();            // run ended inside a block
 }
