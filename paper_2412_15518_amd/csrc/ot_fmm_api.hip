@@ -502,9 +502,9 @@ int setup_device(ot_fmm_plan P)
         v.nby = v.np / v.by;
         const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;
         // full moments where an M2M launch reads them back from memory: the
-        // top level of every span below another span, and level L-1 for the
-        // adjoint's bottom span (the forward forms level L-1 inside it)
-        bool full = (l == L - 1 && d.n_span > 0);
+        // top level of every span below another span (the bottom span forms
+        // level L-1 itself, from the leaf sources)
+        bool full = false;
         for (int i = 1; i < d.n_span; ++i) full = full || (l == d.span_top[i]);
         v.M = nullptr;
         v.Mr = nullptr;
@@ -716,7 +716,7 @@ int ot_fmm_adjoint(ot_fmm_plan P, const double *dphi, const double *dg, double *
     hipError_t e;
     Phase total(P, s, OT_FMM_PHASE_TOTAL, 0);
     {
-        Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF_ADJ, d.n_span > 0 ? 2 : 1);
+        Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF_ADJ, 1);
         if ((e = launch_upward_leaf_adj(d, dphi, dg, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf_adj");
         ph.end();
     }

@@ -15,7 +15,7 @@
 //   so the 64 lanes of a wave that handle 64 neighbouring parents read
 //   consecutive addresses, and the stencil never needs a bounds check.
 //   The leaf sources (masses, or the adjoint's cotangents) are staged in the
-//   same padded form, children innermost: src[plane][ppL^3][8].
+//   same padded form, by pairs of children: src[plane][4][ppL^3][2].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -84,7 +84,7 @@ struct DevPlan {
     int sL;              // leaf sub-grids per axis (2^L)
     int64_t n_leaf_cells;
     const int32_t *leaf_slot;   // [sL^3] leaf index in layout order
-    double *src;                // [4][ppL^3][8]
+    double *src;                // [4][4][ppL^3][2]: plane, child pair, padded parent
     const double *Ktab;         // [OFF_N][4]: K0, K1x, K1y, K1z of a leaf pair
     const double *Kst;          // [n_plist_leaf][27][4]: Ktab rows of 2P + e, e in {-1,0,1}^3
     const double *Ksa;          // [4][n_plist_leaf][27]: the same rows plane by plane for the

@@ -352,20 +352,21 @@ __device__ __forceinline__ void leaf_p2m(const DevPlan &p, const double *__restr
         const int64_t idx = base + ((lz0 + bz) * 8 + (ly0 + by)) * 8 + (lx0 + bx);
         double e[NC];
         taylor(bx ? -hh : hh, by ? -hh : hh, bz ? -hh : hh, e);    // e(z_Q - z_child)
-        // source planes [plane][parent][child]: a parent's 8 children are 64
-        // contiguous bytes
+        // source planes [plane][child pair][parent][2]: one 16-byte load of
+        // 64 neighbouring parents reads 1 KB of contiguous memory
+        const int64_t sp = ((b >> 1) * ppL3 + padQ) * 2 + (b & 1);
         if (!ADJ) {
             const double m = a0[idx] * p.h3;
-            p.src[padQ * 8 + b] = m;
+            p.src[sp] = m;
 #pragma unroll
             for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], m, Mq[k]);
         } else {
             const double w = a0[idx];
             double u[3] = {a1[idx], a1[N + idx], a1[2 * N + idx]};
-            p.src[(0 * ppL3 + padQ) * 8 + b] = w;
-            p.src[(1 * ppL3 + padQ) * 8 + b] = u[0];
-            p.src[(2 * ppL3 + padQ) * 8 + b] = u[1];
-            p.src[(3 * ppL3 + padQ) * 8 + b] = u[2];
+            p.src[sp] = w;
+            p.src[8 * ppL3 + sp] = u[0];
+            p.src[16 * ppL3 + sp] = u[1];
+            p.src[24 * ppL3 + sp] = u[2];
 #pragma unroll
             for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], w, Mq[k]);
             dipole_apply(Mq, e, u);
@@ -453,10 +454,10 @@ __device__ __forceinline__ void span_cell(int ax, int ay, int az, int j, int idx
 // step shifts the moments of child b to the centre of cell ci; the 8
 // children of a cell sit in 8 consecutive lanes and are summed by shuffles
 // in a fixed order.  The children of the deepest cells come from memory
-// (SRC = 0), or, for the bottom span of the forward pass, are the leaf
-// parents themselves, whose moments thread t forms by P2M from the leaf
-// masses and stores (SRC = 1); the other steps take their children from the
-// previous step through LDS.
+// (SRC = 0), or, for the bottom span, are the leaf parents themselves, whose
+// moments thread t forms by P2M from the leaf sources and stores (SRC = 1:
+// the masses of the forward pass, SRC = 2: the adjoint's dual sources); the
+// other steps take their children from the previous step through LDS.
 constexpr int M2M_SPAN_WG = 512;
 
 // four waves per SIMD (at most 128 registers): two 8-wave workgroups per CU,
@@ -481,10 +482,10 @@ void k_m2m_span(const DevPlan p, const double *__restrict__ a0, const double *__
 #pragma unroll
         for (int k = 0; k < NC; ++k) Mc[k] = 0.0;
         if (act) {
-            if (j == nlev - 1 && SRC == 1) {
-                // the child is a leaf parent: P2M from its leaf masses, stored for the M2L
+            if (j == nlev - 1 && SRC >= 1) {
+                // the child is a leaf parent: P2M from its leaf sources, stored for the M2L
                 const int Qx = 2 * cx + (b & 1), Qy = 2 * cy + ((b >> 1) & 1), Qz = 2 * cz + (b >> 2);
-                leaf_p2m<false>(p, a0, a1, Qx, Qy, Qz, Mc);
+                leaf_p2m<SRC == 2>(p, a0, a1, Qx, Qy, Qz, Mc);
                 store_moments(p.lev[lv + 1], Qx, Qy, Qz, Mc, false);
             } else if (j == nlev - 1) {
                 // the children of c are stored under c in level lv + 1
@@ -1050,7 +1051,9 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
     const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
     const int64_t pp = p.ppL;
     const int64_t ppL3 = pp * pp * pp;
-    const double *__restrict__ S = p.src + (((Qz + p.hpL) * pp + (Qy + p.hpL)) * pp + (Qx + p.hpL)) * 8;
+    // this lane's parent in the source planes [plane][child pair][parent][2]
+    const double2 *__restrict__ S =
+        reinterpret_cast<const double2 *>(p.src) + ((Qz + p.hpL) * pp + (Qy + p.hpL)) * pp + (Qx + p.hpL);
 
     constexpr int NA = ADJ ? 1 : 4;     // accumulators per sink child
     double acc[8][NA];
@@ -1071,10 +1074,10 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
         double cur[8], nxt[8];
         auto fetch = [&](int pi, double *dst) {
             const char4 P = plist[pi];
-            const double2 *src = reinterpret_cast<const double2 *>(S + (((int64_t)P.z * pp + P.y) * pp + P.x) * 8);
+            const double2 *src = S + ((int64_t)P.z * pp + P.y) * pp + P.x;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double2 v = src[c];
+                const double2 v = src[c * ppL3];
                 dst[2 * c] = v.x;
                 dst[2 * c + 1] = v.y;
             }
@@ -1113,11 +1116,10 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
         // ring needs no register copies.
         auto fetch = [&](int j, int pi, double *dst) {
             const char4 P = plist[pi];
-            const double2 *src =
-                reinterpret_cast<const double2 *>(S + ((int64_t)j * ppL3 + ((int64_t)P.z * pp + P.y) * pp + P.x) * 8);
+            const double2 *src = S + (int64_t)j * 4 * ppL3 + ((int64_t)P.z * pp + P.y) * pp + P.x;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double2 v = src[c];
+                const double2 v = src[c * ppL3];
                 dst[2 * c] = v.x;
                 dst[2 * c + 1] = v.y;
             }
@@ -1195,21 +1197,19 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
 static inline unsigned grid_x8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
 
-// upward pass up to the bottom M2M span.  Forward: P2M into level L-1 fused
-// with the bottom span.  Adjoint: its P2M moves four planes each way per leaf
-// cell, which a fused launch would serialise with the span's reduction, so it
-// runs as its own launch followed by the span.  Depths 0 and 1 have no span.
+// upward pass up to the bottom M2M span: P2M into level L-1 fused with the
+// bottom span (src 1: forward, 2: adjoint).  Depths 0 and 1 have no span and
+// run the P2M alone.
 static hipError_t launch_upward_leaf(const DevPlan &p, int src, const double *a0, const double *a1, hipStream_t s)
 {
     const int last = p.n_span - 1;
     const int64_t nq = (int64_t)p.npL * p.npL * p.npL;
-    if (last < 0 || src == 2) {
+    if (last < 0) {
         if (src == 1)
             hipLaunchKernelGGL(k_upward_leaf<false>, dim3(grid_for(nq)), dim3(WG), 0, s, p, a0, a1);
         else
             hipLaunchKernelGGL(k_upward_leaf<true>, dim3(grid_for(nq)), dim3(WG), 0, s, p, a0, a1);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess || last < 0) return e;
+        return hipGetLastError();
     }
     const int t = p.span_top[last], nl = p.span_n[last];
     const int64_t n = 8 << t;
@@ -1217,7 +1217,7 @@ static hipError_t launch_upward_leaf(const DevPlan &p, int src, const double *a0
     if (src == 1)
         hipLaunchKernelGGL(k_m2m_span<1>, grid, block, 0, s, p, a0, a1, t, nl);
     else
-        hipLaunchKernelGGL(k_m2m_span<0>, grid, block, 0, s, p, nullptr, nullptr, t, nl);
+        hipLaunchKernelGGL(k_m2m_span<2>, grid, block, 0, s, p, a0, a1, t, nl);
     return hipGetLastError();
 }
 
