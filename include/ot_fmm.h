@@ -69,9 +69,9 @@ extern "C" {
                                         FP32 and then added to FP64 accumulators;
                                         every other stage stays FP64.  The paper's
                                         runs are FP64 (its data-set table, Sec. 6.1):
-                                        this is an optional faster M2L whose result
-                                        differs from the FP64 one by about 1e-7
-                                        normwise (bounded by 1e-5 in the tests).
+                                        this is an optional lower-precision M2L whose
+                                        result differs from the FP64 one by about
+                                        1e-7 normwise (bounded by 1e-5 in the tests).
                                         Moments must stay inside the FP32 range. */
 
 typedef struct ot_fmm_plan_s *ot_fmm_plan;   /* opaque */

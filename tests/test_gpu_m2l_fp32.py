@@ -1,13 +1,13 @@
 """GPU parity of the FP32 M2L (plan flag OT_FMM_M2L_FP32) against the FP64
 oracle and against the library's own FP64 path, through the C ABI.
 
-Tolerance.  The FP32 path rounds the moments and derivative tensors to FP32
-(relative error u = 2^-24 ~ 6e-8 each) and sums the products of one parent
-offset (at most 8 source children x 20 terms per output component) in FP32
-before adding them to FP64 accumulators.  A sum of n products carries at most
-about n u relative to the sum of their magnitudes, so each parent offset's
-contribution to a local coefficient is off by at most ~160 u ~ 1e-5 of its
-absolute sum.  The local expansion is dominated by a few such contributions
+Tolerance.  The FP32 path rounds the (reduced) moments and derivative tensors
+to FP32 (relative error u = 2^-24 ~ 6e-8 each) and sums the products of one
+parent offset (at most 8 source children x 16 terms per output component) in
+FP32 before adding them to FP64 accumulators.  A sum of n products carries at
+most about n u relative to the sum of their magnitudes, so each parent
+offset's contribution to a local coefficient is off by at most ~128 u ~ 1e-5
+of its absolute sum.  The local expansion is dominated by a few such contributions
 and everything downstream (L2L, L2P, leaf P2P) is FP64, so the normwise error
 max|d phi| / max|phi| (and the same for g) is bounded by ~1e-5; measured
 values are around 1e-7 and are printed.
