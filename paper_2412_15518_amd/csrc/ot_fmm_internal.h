@@ -35,9 +35,10 @@ constexpr int OFF_R = 7;                        // offset tables span [-7, 7]^3
 constexpr int OFF_W = 2 * OFF_R + 1;
 constexpr int OFF_N = OFF_W * OFF_W * OFF_W;    // 3375
 constexpr int MAX_LEVELS = 8;                   // per-level arrays in the plan
-// deepest supported leaf level: the M2L stencil offsets of a level are 32-bit
-// (component x child x padded parent grid, 3.7e8 at the deepest M2L level of
-// depth 6; depth 7 would overflow them)
+// deepest supported leaf level.  The M2L forms a level's offsets in 32 bits
+// (component group x child x padded parent grid: 1.5e8 at the deepest M2L
+// level of depth 6, 1.1e9 at depth 7, with no margin beyond); depth 7 is
+// untested and would need about 100 GB of plan memory.
 constexpr int MAX_DEPTH = 6;
 constexpr int WG = 256;                         // threads per workgroup (4 waves)
 
