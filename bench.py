@@ -13,7 +13,9 @@ pairs plus M2L pairs of the coarser levels) per second over the K timed steps.
 untimed pass that records every phase; the per-phase breakdown comes from that
 pass), timed by HIP events around its launches inside the timed region, against
 the FP64 vector peak of the MI355X.  `cpu_baseline` times the CPU
-oracle (forward + adjoint) on a z-slab of the same workload.
+oracle (forward + adjoint) on a z-slab of the same workload.  `m2l_fp32` times
+the FP32 M2L plan on the same workload; `batch` times 16 independent small
+octrees plan by plan, as one batch over 4 streams and as HIP graph replays.
 """
 import argparse
 import hashlib
@@ -82,6 +84,78 @@ def phase_flops(phase: str, info: dict) -> float:
             "l2l": 168.0 * cells(1, L - 1)}[phase]
 
 
+def bench_batch(args) -> dict:
+    """16 independent octrees (leaf counts log-uniform in [64, 1024], seed 3,
+    as uniform trees of depth 2 or 3): forward + adjoint of all of them per
+    step, plan by plan on one stream, as one batch over 4 streams, and as the
+    replay of that batch captured in two HIP graphs."""
+    import numpy as np
+    import torch
+
+    from paper_2412_15518_amd import fmm, workloads as W
+    trees = W.batch_of_octrees()
+    plans, rhos, ws, us, phis, gs, drhos = [], [], [], [], [], [], []
+    pairs = 0
+    for t in trees:
+        lay = W.uniform_layout(t["L"])
+        p = fmm.Plan(lay)
+        inf = p.info()
+        pairs += 2 * (inf["p2p_pairs"] + inf["m2l_pairs"])
+        dev = lambda a, lay=lay: torch.from_numpy(lay.dense_to_layout(np.ascontiguousarray(a))).cuda()  # noqa: E731
+        plans.append(p)
+        rhos.append(dev(t["rho"]))
+        ws.append(dev(t["w"]))
+        us.append(dev(t["u"]).reshape(-1))
+        phis.append(torch.empty_like(rhos[-1]))
+        gs.append(torch.empty(3 * rhos[-1].numel(), dtype=torch.float64, device="cuda"))
+        drhos.append(torch.empty_like(rhos[-1]))
+    ns = 4
+    b = fmm.Batch(plans, n_streams=ns)
+    gf = b.capture_forward(rhos, phis, gs)
+    ga = b.capture_adjoint(ws, us, drhos)
+
+    def single():
+        for i, p in enumerate(plans):
+            p.forward_into(rhos[i], phis[i], gs[i])
+            p.adjoint_into(ws[i], us[i], drhos[i])
+
+    def batched():
+        b.forward_into(rhos, phis, gs)
+        b.adjoint_into(ws, us, drhos)
+
+    def graphs():
+        gf.launch()
+        ga.launch()
+
+    k = max(5, min(args.steps, 50))
+    res = {}
+    outs = {}
+    for name, fn in (("single", single), ("batch", batched), ("graph", graphs)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = 1e3 * (time.perf_counter() - t0) / k
+        outs[name] = [x.clone() for x in phis + gs + drhos]
+    same = all(torch.equal(a, c) for n in ("batch", "graph") for a, c in zip(outs[n], outs["single"]))
+    gf.close()
+    ga.close()
+    b.close()
+    log(f"batch of {len(trees)} trees: single {res['single']:.3f} ms, batch {res['batch']:.3f} ms, "
+        f"graph {res['graph']:.3f} ms per step")
+    return {"workload": f"{len(trees)} octrees, leaf counts log-uniform in [64, 1024] (seed 3) as uniform trees "
+                        f"of depth {sorted(set(t['L'] for t in trees))}, "
+                        f"{sum(8 ** t['L'] for t in trees)} sub-grids; one step = forward + adjoint of every tree",
+            "steps": k, "streams": ns, "cell_interactions_per_step": pairs,
+            "ms_per_step": res, "cell_interactions_per_s_graph": pairs / (res["graph"] * 1e-3),
+            "speedup_graph_vs_single": res["single"] / res["graph"],
+            "speedup_batch_vs_single": res["single"] / res["batch"],
+            "outputs_identical": same}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +163,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-slab", type=int, default=64,
                     help="leaf z-layers of the 128^3 grid in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="also time the batch of 16 independent octrees (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before warmup, copy this many MiB device to device once: a plain copy "
                          "kernel of known traffic that calibrates HBM counter readings")
@@ -243,6 +319,9 @@ def main():
                              "g_rel_l2": float((g32 - g).norm() / g.norm()),
                              "norm": "normwise max-abs (g: per-cell Euclidean) and relative L2, whole grid"},
         "note": "M2L in FP32 with FP64 accumulation per parent offset; unpacked FP32 issues at the FP64 rate"}
+
+    if args.batch:
+        out["batch"] = bench_batch(args)
 
     if args.cpu_slab > 0:
         import oracle as O

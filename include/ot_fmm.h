@@ -171,6 +171,56 @@ int ot_fmm_timing_phases(ot_fmm_plan plan, uint32_t phase_mask);
 int ot_fmm_timing_end(ot_fmm_plan plan, ot_fmm_timing *out);
 const char *ot_fmm_phase_name(int phase);
 
+/* ---- batches of independent octrees ---------------------------------------
+ * The paper runs many small sub-grid kernels concurrently and fuses them to
+ * keep the GPU busy (Sec. 5.3, dynamic work aggregation and the executor
+ * pools of its HPX/Kokkos runtime).  A batch does the same for independent
+ * plans: one call enqueues the forward (or adjoint) of every plan, spread over
+ * a few internal HIP streams so that small trees run side by side, and joins
+ * them back into the caller's stream.  The same enqueue sequence can be
+ * captured once into a HIP graph and replayed, which removes the per-launch
+ * host cost of the many small kernels.
+ *
+ * A batch does not own its plans: they must outlive it, and no plan may run
+ * elsewhere while a batch call or graph replay that uses it is in flight (a
+ * plan's scratch is shared by all its calls).  Every plan lives on the same
+ * device; a plan appears at most once in a batch. */
+typedef struct ot_fmm_batch_s *ot_fmm_batch;   /* opaque */
+typedef struct ot_fmm_graph_s *ot_fmm_graph;   /* opaque */
+
+/* n >= 1 plans with device state; n_streams in [1, 16] internal streams (at
+ * most n are used; plan i runs on stream i mod n_streams).  The streams and
+ * events are created here at default priority. */
+int ot_fmm_batch_create(const ot_fmm_plan *plans, int n, int n_streams, ot_fmm_batch *out);
+
+/* Forward of every plan i: rho[i] -> phi[i], g[i] (host arrays of n device
+ * pointers, each as in ot_fmm_forward).  Work is ordered after everything
+ * enqueued on hip_stream before the call, and everything enqueued on it
+ * afterwards waits for all n plans.  Pointers are checked before any work is
+ * enqueued. */
+int ot_fmm_batch_forward(ot_fmm_batch b, const double *const *rho, double *const *phi, double *const *g,
+                         void *hip_stream);
+/* Adjoint of every plan i: dphi[i], dg[i] -> drho[i], as in ot_fmm_adjoint. */
+int ot_fmm_batch_adjoint(ot_fmm_batch b, const double *const *dphi, const double *const *dg,
+                         double *const *drho, void *hip_stream);
+
+/* Capture the batch forward (or adjoint) for these fixed device buffers into
+ * an executable HIP graph.  Kernel timing must be off for every plan (no
+ * timing_begin without timing_end).  The graph records the buffer addresses:
+ * a replay reads and writes the same buffers. */
+int ot_fmm_batch_capture_forward(ot_fmm_batch b, const double *const *rho, double *const *phi,
+                                 double *const *g, ot_fmm_graph *out);
+int ot_fmm_batch_capture_adjoint(ot_fmm_batch b, const double *const *dphi, const double *const *dg,
+                                 double *const *drho, ot_fmm_graph *out);
+
+/* Replay a captured graph on hip_stream (NULL = the default stream). */
+int ot_fmm_graph_launch(ot_fmm_graph g, void *hip_stream);
+
+/* Release a graph or a batch (NULL is a no-op); the device must be idle for
+ * the work they enqueued. */
+void ot_fmm_graph_destroy(ot_fmm_graph g);
+void ot_fmm_batch_destroy(ot_fmm_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -593,6 +593,114 @@ hipError_t tree_passes(ot_fmm_plan P, hipStream_t s)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// batches of independent plans: a fork over a few internal streams and a join
+// back into the caller's stream, enqueued eagerly or captured into a graph
+// ---------------------------------------------------------------------------
+struct ot_fmm_batch_s {
+    std::vector<ot_fmm_plan> plans;
+    int device = -1;
+    std::vector<hipStream_t> streams;   // internal, default priority
+    hipEvent_t fork = nullptr;          // recorded on the caller's stream
+    std::vector<hipEvent_t> join;       // one per internal stream
+};
+
+struct ot_fmm_graph_s {
+    int device = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int BATCH_MAX_STREAMS = 16;
+
+void release_batch(ot_fmm_batch B)
+{
+    for (hipStream_t s : B->streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t ev : B->join) (void)hipEventDestroy(ev);
+    if (B->fork) (void)hipEventDestroy(B->fork);
+    delete B;
+}
+
+// every pointer of the n argument triples present and 8-byte aligned
+int check_batch_args(ot_fmm_batch B, const void *const *a, const void *const *b, const void *const *c)
+{
+    if (!B) return fail(OT_FMM_INVALID_ARGUMENT, "batch is NULL");
+    if (!a || !b || !c) return fail(OT_FMM_INVALID_ARGUMENT, "NULL pointer array");
+    for (size_t i = 0; i < B->plans.size(); ++i) {
+        if (!a[i] || !b[i] || !c[i]) return fail(OT_FMM_INVALID_ARGUMENT, "NULL device pointer in a batch");
+        if (misaligned(a[i]) || misaligned(b[i]) || misaligned(c[i]))
+            return fail(OT_FMM_INVALID_ARGUMENT, "device pointers must be 8-byte aligned");
+    }
+    return OT_FMM_OK;
+}
+
+// fork from s, run plan i on internal stream i mod n_streams, join into s.
+// The join is enqueued even after a failed launch, so that a capture stays
+// well formed; the first failure is returned.
+template <typename F>
+int batch_enqueue(ot_fmm_batch B, hipStream_t s, F run_plan)
+{
+    const size_t ns = B->streams.size();
+    hipError_t e = hipEventRecord(B->fork, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord (batch fork)");
+    for (size_t k = 0; k < ns; ++k)
+        if ((e = hipStreamWaitEvent(B->streams[k], B->fork, 0)) != hipSuccess)
+            return hip_fail(e, "hipStreamWaitEvent (batch fork)");
+    int rc = OT_FMM_OK;
+    for (size_t i = 0; i < B->plans.size() && rc == OT_FMM_OK; ++i) rc = run_plan(i, B->streams[i % ns]);
+    for (size_t k = 0; k < ns; ++k) {
+        if ((e = hipEventRecord(B->join[k], B->streams[k])) != hipSuccess ||
+            (e = hipStreamWaitEvent(s, B->join[k], 0)) != hipSuccess) {
+            if (rc == OT_FMM_OK) rc = hip_fail(e, "batch join");
+        }
+    }
+    return rc;
+}
+
+// capture one enqueue of the batch into an executable graph, on a stream of
+// its own
+template <typename F>
+int batch_capture(ot_fmm_batch B, F enqueue, ot_fmm_graph *out)
+{
+    for (ot_fmm_plan P : B->plans)
+        if (P->timing.active)
+            return fail(OT_FMM_INVALID_ARGUMENT, "kernel timing is active on a plan of the batch; end it before capturing");
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags (capture)");
+    ot_fmm_graph G = new (std::nothrow) ot_fmm_graph_s();
+    if (!G) {
+        (void)hipStreamDestroy(cs);
+        return fail(OT_FMM_OUT_OF_MEMORY, "host allocation of the graph failed");
+    }
+    G->device = B->device;
+    int rc = OT_FMM_OK;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        rc = hip_fail(e, "hipStreamBeginCapture");
+    } else {
+        rc = enqueue(cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (rc == OT_FMM_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+        G->graph = g;
+        if (rc == OT_FMM_OK && (e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+            rc = hip_fail(e, "hipGraphInstantiate");
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != OT_FMM_OK) {
+        if (G->exec) (void)hipGraphExecDestroy(G->exec);
+        if (G->graph) (void)hipGraphDestroy(G->graph);
+        delete G;
+        return rc;
+    }
+    *out = G;
+    return OT_FMM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *ot_fmm_status_string(int s)
@@ -787,6 +895,124 @@ int ot_fmm_timing_end(ot_fmm_plan P, ot_fmm_timing *out)
     for (hipEvent_t ev : T.pool) (void)hipEventDestroy(ev);
     T = TimingState{};
     return rc;
+}
+
+int ot_fmm_batch_create(const ot_fmm_plan *plans, int n, int n_streams, ot_fmm_batch *out)
+{
+    if (!out) return fail(OT_FMM_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (!plans || n < 1) return fail(OT_FMM_INVALID_ARGUMENT, "a batch needs at least one plan");
+    if (n_streams < 1 || n_streams > BATCH_MAX_STREAMS)
+        return fail(OT_FMM_INVALID_ARGUMENT, "n_streams must lie in [1, 16]");
+    std::unordered_set<const void *> seen;
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(OT_FMM_INVALID_ARGUMENT, "NULL plan in a batch");
+        if (!plans[i]->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "a plan of the batch was created with OT_FMM_HOST_ONLY");
+        if (plans[i]->device != plans[0]->device) return fail(OT_FMM_INVALID_ARGUMENT, "the plans of a batch live on different devices");
+        if (!seen.insert(plans[i]).second) return fail(OT_FMM_INVALID_ARGUMENT, "a plan appears twice in a batch");
+    }
+    ot_fmm_batch B = new (std::nothrow) ot_fmm_batch_s();
+    if (!B) return fail(OT_FMM_OUT_OF_MEMORY, "host allocation of the batch failed");
+    try {
+        B->plans.assign(plans, plans + n);
+    } catch (const std::bad_alloc &) {
+        delete B;
+        return fail(OT_FMM_OUT_OF_MEMORY, "host allocation of the batch failed");
+    }
+    B->device = plans[0]->device;
+    DeviceGuard guard(B->device);
+    const int ns = std::min(n, n_streams);
+    hipError_t e = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming);
+    for (int k = 0; k < ns && e == hipSuccess; ++k) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) break;
+        B->streams.push_back(st);
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) break;
+        B->join.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        release_batch(B);
+        return hip_fail(e, "batch streams and events");
+    }
+    *out = B;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_batch_forward(ot_fmm_batch B, const double *const *rho, double *const *phi, double *const *g,
+                         void *hip_stream)
+{
+    int rc = check_batch_args(B, (const void *const *)rho, (const void *const *)phi, (const void *const *)g);
+    if (rc) return rc;
+    DeviceGuard guard(B->device);
+    return batch_enqueue(B, static_cast<hipStream_t>(hip_stream), [&](size_t i, hipStream_t st) {
+        return ot_fmm_forward(B->plans[i], rho[i], phi[i], g[i], st);
+    });
+}
+
+int ot_fmm_batch_adjoint(ot_fmm_batch B, const double *const *dphi, const double *const *dg,
+                         double *const *drho, void *hip_stream)
+{
+    int rc = check_batch_args(B, (const void *const *)dphi, (const void *const *)dg, (const void *const *)drho);
+    if (rc) return rc;
+    DeviceGuard guard(B->device);
+    return batch_enqueue(B, static_cast<hipStream_t>(hip_stream), [&](size_t i, hipStream_t st) {
+        return ot_fmm_adjoint(B->plans[i], dphi[i], dg[i], drho[i], st);
+    });
+}
+
+int ot_fmm_batch_capture_forward(ot_fmm_batch B, const double *const *rho, double *const *phi,
+                                 double *const *g, ot_fmm_graph *out)
+{
+    if (!out) return fail(OT_FMM_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    int rc = check_batch_args(B, (const void *const *)rho, (const void *const *)phi, (const void *const *)g);
+    if (rc) return rc;
+    DeviceGuard guard(B->device);
+    return batch_capture(B, [&](hipStream_t cs) {
+        return batch_enqueue(B, cs, [&](size_t i, hipStream_t st) {
+            return ot_fmm_forward(B->plans[i], rho[i], phi[i], g[i], st);
+        });
+    }, out);
+}
+
+int ot_fmm_batch_capture_adjoint(ot_fmm_batch B, const double *const *dphi, const double *const *dg,
+                                 double *const *drho, ot_fmm_graph *out)
+{
+    if (!out) return fail(OT_FMM_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    int rc = check_batch_args(B, (const void *const *)dphi, (const void *const *)dg, (const void *const *)drho);
+    if (rc) return rc;
+    DeviceGuard guard(B->device);
+    return batch_capture(B, [&](hipStream_t cs) {
+        return batch_enqueue(B, cs, [&](size_t i, hipStream_t st) {
+            return ot_fmm_adjoint(B->plans[i], dphi[i], dg[i], drho[i], st);
+        });
+    }, out);
+}
+
+int ot_fmm_graph_launch(ot_fmm_graph G, void *hip_stream)
+{
+    if (!G || !G->exec) return fail(OT_FMM_INVALID_ARGUMENT, "graph is NULL");
+    DeviceGuard guard(G->device);
+    hipError_t e = hipGraphLaunch(G->exec, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+void ot_fmm_graph_destroy(ot_fmm_graph G)
+{
+    if (!G) return;
+    DeviceGuard guard(G->device);
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+}
+
+void ot_fmm_batch_destroy(ot_fmm_batch B)
+{
+    if (!B) return;
+    DeviceGuard guard(B->device);
+    release_batch(B);
 }
 
 }  // extern "C"

@@ -34,7 +34,9 @@ PHASES = ["upward_leaf", "m2m", "m2l", "l2l", "leaf", "upward_leaf_adj", "leaf_a
 
 EXPORTS = ["ot_fmm_plan_create", "ot_fmm_forward", "ot_fmm_adjoint", "ot_fmm_plan_info",
            "ot_fmm_destroy", "ot_fmm_status_string", "ot_fmm_last_error", "ot_fmm_timing_begin",
-           "ot_fmm_timing_end", "ot_fmm_phase_name", "ot_fmm_timing_phases"]
+           "ot_fmm_timing_end", "ot_fmm_phase_name", "ot_fmm_timing_phases", "ot_fmm_batch_create",
+           "ot_fmm_batch_forward", "ot_fmm_batch_adjoint", "ot_fmm_batch_capture_forward",
+           "ot_fmm_batch_capture_adjoint", "ot_fmm_graph_launch", "ot_fmm_graph_destroy", "ot_fmm_batch_destroy"]
 
 
 class OTFMMError(RuntimeError):
@@ -96,6 +98,21 @@ def load_library():
     lib.ot_fmm_phase_name.restype = C.c_char_p
     lib.ot_fmm_timing_phases.argtypes = [vp, C.c_uint32]
     lib.ot_fmm_timing_phases.restype = C.c_int
+    pp = C.POINTER(vp)
+    lib.ot_fmm_batch_create.argtypes = [pp, C.c_int, C.c_int, C.POINTER(vp)]
+    lib.ot_fmm_batch_create.restype = C.c_int
+    for name in ("ot_fmm_batch_forward", "ot_fmm_batch_adjoint"):
+        getattr(lib, name).argtypes = [vp, pp, pp, pp, vp]
+        getattr(lib, name).restype = C.c_int
+    for name in ("ot_fmm_batch_capture_forward", "ot_fmm_batch_capture_adjoint"):
+        getattr(lib, name).argtypes = [vp, pp, pp, pp, C.POINTER(vp)]
+        getattr(lib, name).restype = C.c_int
+    lib.ot_fmm_graph_launch.argtypes = [vp, vp]
+    lib.ot_fmm_graph_launch.restype = C.c_int
+    lib.ot_fmm_graph_destroy.argtypes = [vp]
+    lib.ot_fmm_graph_destroy.restype = None
+    lib.ot_fmm_batch_destroy.argtypes = [vp]
+    lib.ot_fmm_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -219,6 +236,91 @@ class Plan:
         return {"calls": t.calls,
                 "phases": {PHASES[i]: {"launches": t.launches[i], "events": t.events[i], "ms": t.ms[i]}
                            for i in range(NUM_PHASES)}}
+
+
+def _ptrs(tensors):
+    return (C.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+class Graph:
+    """A captured batch call (ot_fmm_batch_capture_*): launch() replays it on
+    the current torch stream, on the buffers it was captured with."""
+
+    def __init__(self, handle, keep):
+        self._handle = handle
+        self._keep = keep           # the captured buffers stay alive with the graph
+
+    def launch(self):
+        import torch
+        _check(load_library().ot_fmm_graph_launch(self._handle, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            load_library().ot_fmm_graph_destroy(self._handle)
+            self._handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Forward or adjoint of several independent plans in one call, spread
+    over n_streams internal streams (ot_fmm_batch_*).  The plans must outlive
+    the batch."""
+
+    def __init__(self, plans, n_streams: int = 4):
+        self.plans = list(plans)
+        handles = (C.c_void_p * len(self.plans))(*[p._handle.value for p in self.plans])
+        self._handle = C.c_void_p()
+        _check(load_library().ot_fmm_batch_create(handles, len(self.plans), int(n_streams), C.byref(self._handle)))
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            load_library().ot_fmm_batch_destroy(self._handle)
+            self._handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_lists(self, lists, specs):
+        for lst, (ncomp, name) in zip(lists, specs):
+            if len(lst) != len(self.plans):
+                raise ValueError(f"{name} needs one tensor per plan")
+            for p, t in zip(self.plans, lst):
+                p._check_field(t, ncomp, name)
+
+    def _stream(self):
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def forward_into(self, rhos, phis, gs):
+        self._check_lists((rhos, phis, gs), ((1, "rho"), (1, "phi"), (3, "g")))
+        _check(load_library().ot_fmm_batch_forward(self._handle, _ptrs(rhos), _ptrs(phis), _ptrs(gs), self._stream()))
+
+    def adjoint_into(self, dphis, dgs, drhos):
+        self._check_lists((dphis, dgs, drhos), ((1, "dphi"), (3, "dg"), (1, "drho")))
+        _check(load_library().ot_fmm_batch_adjoint(self._handle, _ptrs(dphis), _ptrs(dgs), _ptrs(drhos),
+                                                   self._stream()))
+
+    def capture_forward(self, rhos, phis, gs) -> Graph:
+        self._check_lists((rhos, phis, gs), ((1, "rho"), (1, "phi"), (3, "g")))
+        h = C.c_void_p()
+        _check(load_library().ot_fmm_batch_capture_forward(self._handle, _ptrs(rhos), _ptrs(phis), _ptrs(gs),
+                                                           C.byref(h)))
+        return Graph(h, (list(rhos), list(phis), list(gs)))
+
+    def capture_adjoint(self, dphis, dgs, drhos) -> Graph:
+        self._check_lists((dphis, dgs, drhos), ((1, "dphi"), (3, "dg"), (1, "drho")))
+        h = C.c_void_p()
+        _check(load_library().ot_fmm_batch_capture_adjoint(self._handle, _ptrs(dphis), _ptrs(dgs), _ptrs(drhos),
+                                                           C.byref(h)))
+        return Graph(h, (list(dphis), list(dgs), list(drhos)))
 
 
 def _make_function():

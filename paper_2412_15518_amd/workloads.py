@@ -238,6 +238,35 @@ def cfg5_lognormal(n: int = 64, seed: int = 5, n_fd: int = 64):
     return dict(L=L, rho=rho, w=w, u=u, cells=cells)
 
 
+def batch_of_octrees(count: int = 16, seed: int = 3, lo: int = 64, hi: int = 1024):
+    """Independent octrees for the batched path: leaf sub-grid counts drawn
+    log-uniform in [lo, hi], each rounded in log scale to the uniform tree with
+    8^L leaf sub-grids (the library's octrees have all leaves on one level, so
+    [64, 1024] gives L = 2 or 3).  Each tree holds either a uniform sphere or an
+    n = 1.5 polytrope at a random centre, on a 1e-10 floor, plus cotangents
+    w, u ~ N(0,1).  Drawn in the order: counts, then per tree kind, centre,
+    radius, rho_c, w, u."""
+    rng = np.random.default_rng(seed)
+    counts = np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))
+    trees = []
+    for c in counts:
+        L = max(1, int(round(math.log(c) / math.log(8.0))))
+        n = SUBGRID << L
+        kind = "sphere" if rng.uniform() < 0.5 else "polytrope"
+        centre = tuple(rng.uniform(0.3 * n, 0.7 * n, size=3))
+        radius = float(rng.uniform(0.15 * n, 0.35 * n))
+        rho_c = float(rng.uniform(0.5, 1.0))
+        if kind == "sphere":
+            rho = uniform_sphere(n, radius, centre, rho_c)
+        else:
+            rho = polytrope(n, centre, radius, rho_c)
+        rho = rho + 1e-10
+        w = rng.standard_normal((n, n, n))
+        u = rng.standard_normal((3, n, n, n))
+        trees.append(dict(L=L, n=n, kind=kind, leaf_count=float(c), rho=rho, w=w, u=u))
+    return trees
+
+
 def random_density(n: int, seed: int, kind: str = "uniform") -> np.ndarray:
     """Plain random fields for small parity cases."""
     rng = np.random.default_rng(seed)

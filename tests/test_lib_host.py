@@ -95,6 +95,37 @@ def test_null_arguments():
     assert h.value is None
 
 
+def test_batch_argument_errors():
+    """Batch and graph entry points reject bad arguments before touching the
+    device; a batch of host-only plans reports NO_DEVICE_STATE."""
+    import ctypes as C
+    lib = fmm.load_library()
+    h = C.c_void_p()
+    assert lib.ot_fmm_batch_create(None, 1, 1, C.byref(h)) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_create(None, 1, 1, None) == fmm.INVALID_ARGUMENT
+    p = fmm.Plan(W.uniform_layout(1), host_only=True)
+    q = fmm.Plan(W.uniform_layout(1), host_only=True)
+    one = (C.c_void_p * 1)(p._handle.value)
+    two_same = (C.c_void_p * 2)(p._handle.value, p._handle.value)
+    nulls = (C.c_void_p * 2)(None, None)
+    assert lib.ot_fmm_batch_create(one, 0, 1, C.byref(h)) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_create(one, 1, 0, C.byref(h)) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_create(one, 1, 17, C.byref(h)) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_create(nulls, 2, 1, C.byref(h)) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_create(one, 1, 1, C.byref(h)) == fmm.NO_DEVICE_STATE
+    assert lib.ot_fmm_batch_create(two_same, 2, 1, C.byref(h)) == fmm.NO_DEVICE_STATE
+    assert h.value is None
+    assert q._handle.value != p._handle.value
+    ptrs = (C.c_void_p * 1)(8)
+    assert lib.ot_fmm_batch_forward(None, ptrs, ptrs, ptrs, None) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_adjoint(None, ptrs, ptrs, ptrs, None) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_capture_forward(None, ptrs, ptrs, ptrs, C.byref(h)) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_batch_capture_adjoint(None, ptrs, ptrs, ptrs, None) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_graph_launch(None, None) == fmm.INVALID_ARGUMENT
+    lib.ot_fmm_graph_destroy(None)      # no-ops
+    lib.ot_fmm_batch_destroy(None)
+
+
 def test_flags():
     """OT_FMM_M2L_FP32 is accepted (and changes no host-side count); unknown
     flag bits are rejected."""
