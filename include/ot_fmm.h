@@ -73,6 +73,14 @@ extern "C" {
                                         result differs from the FP64 one by about
                                         1e-7 normwise (bounded by 1e-5 in the tests).
                                         Moments must stay inside the FP32 range. */
+#define OT_FMM_AUTOTUNE   (1u << 2)  /* pick the stencil chunk count of each leaf pass
+                                        (1, 2, 4 or 8 waves per block of 64 leaf
+                                        parents) by timing them at plan creation;
+                                        without it the count follows from the tree
+                                        size (at least ~2048 waves per launch).
+                                        Results of different counts agree to
+                                        rounding; a plan keeps its counts, so its
+                                        calls repeat bit for bit. */
 
 typedef struct ot_fmm_plan_s *ot_fmm_plan;   /* opaque */
 
@@ -110,6 +118,8 @@ typedef struct {
     double  bytes_forward;         /* algorithmic HBM bytes per forward */
     double  bytes_adjoint;
     size_t  device_bytes;          /* device memory owned by the plan */
+    int32_t leaf_chunks_forward;   /* stencil chunks (waves per leaf block) of the forward leaf pass */
+    int32_t leaf_chunks_adjoint;   /* the same for the adjoint */
 } ot_fmm_info;
 
 /* Validate `layout`, build the interaction tables and allocate all device
@@ -131,6 +141,13 @@ int ot_fmm_adjoint(ot_fmm_plan plan, const double *dphi, const double *dg,
                    double *drho, void *hip_stream);
 
 int ot_fmm_plan_info(ot_fmm_plan plan, ot_fmm_info *info);
+
+/* Set the stencil chunk counts (waves per block of 64 leaf parents, each
+ * summing a contiguous part of the parent-offset list) of the forward and
+ * adjoint leaf passes, overriding the size rule or the autotuner; each in
+ * [1, 8].  Counts outside it are INVALID_ARGUMENT, a host-only plan
+ * NO_DEVICE_STATE.  Calls enqueued afterwards use the new counts. */
+int ot_fmm_plan_set_leaf_chunks(ot_fmm_plan plan, int forward, int adjoint);
 
 /* Releases the plan and its device memory (the device must be idle for it).
  * NULL is a no-op. */

@@ -447,6 +447,48 @@ void free_device(ot_fmm_plan P)
     P->timing.pool.clear();
 }
 
+// Time each leaf pass with 1, 2, 4 and 8 stencil chunks (a warm-up launch,
+// then the best of three single launches, on the plan's zeroed scratch and
+// temporary outputs) and keep the fastest count.
+int autotune_leaf(ot_fmm_plan P)
+{
+    DevPlan &d = P->dp;
+    const size_t N = (size_t)d.n_leaf_cells;
+    double *o0 = nullptr, *o1 = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipMalloc(&o0, N * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&o1, 3 * N * sizeof(double));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    for (int adj = 0; adj < 2 && e == hipSuccess; ++adj) {
+        float best = 0.0f;
+        for (int c = 1; c <= LEAF_MAX_CHUNKS && e == hipSuccess; c *= 2) {
+            float tmin = 0.0f;
+            for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+                if ((e = hipEventRecord(ev[0], st)) != hipSuccess) break;
+                if ((e = launch_leaf_chunks(d, adj, c, o0, o1, st)) != hipSuccess) break;
+                if ((e = hipEventRecord(ev[1], st)) != hipSuccess) break;
+                if ((e = hipEventSynchronize(ev[1])) != hipSuccess) break;
+                float ms = 0.0f;
+                if ((e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) break;
+                if (rep > 0 && (rep == 1 || ms < tmin)) tmin = ms;     // launch 0 warms up
+            }
+            if (e == hipSuccess && (c == 1 || tmin < best)) {
+                best = tmin;
+                d.leaf_chunks[adj] = c;
+            }
+        }
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (st) (void)hipStreamDestroy(st);
+    if (o1) (void)hipFree(o1);
+    if (o0) (void)hipFree(o0);
+    return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "leaf autotuning");
+}
+
 int setup_device(ot_fmm_plan P)
 {
     hipError_t e = hipGetDevice(&P->device);
@@ -519,8 +561,15 @@ int setup_device(ot_fmm_plan P)
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }
+    // stencil chunks of the leaf passes: enough waves for at least ~2048 per
+    // launch (two per SIMD), at most LEAF_MAX_CHUNKS per block
+    const int64_t nblk = (int64_t)d.npL * d.npL * d.npL / 64;
+    int c = 1;
+    while (c < LEAF_MAX_CHUNKS && nblk * c < 2048) c *= 2;
+    d.leaf_chunks[0] = d.leaf_chunks[1] = c;
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize after plan setup");
+    if ((P->flags & OT_FMM_AUTOTUNE) && (rc = autotune_leaf(P))) return rc;
     P->has_device = true;
     return OT_FMM_OK;
 }
@@ -733,7 +782,8 @@ int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order, 
 {
     if (!out) return fail(OT_FMM_INVALID_ARGUMENT, "out is NULL");
     *out = nullptr;
-    if (flags & ~(OT_FMM_HOST_ONLY | OT_FMM_M2L_FP32)) return fail(OT_FMM_INVALID_ARGUMENT, "unknown flag bits");
+    if (flags & ~(OT_FMM_HOST_ONLY | OT_FMM_M2L_FP32 | OT_FMM_AUTOTUNE))
+        return fail(OT_FMM_INVALID_ARGUMENT, "unknown flag bits");
     if (!std::isfinite(theta) || theta <= 0.0) return fail(OT_FMM_INVALID_ARGUMENT, "theta must be finite and > 0");
     if (!(theta > 1.0 / 3.0 && theta <= 1.0))
         return fail(OT_FMM_UNSUPPORTED_THETA, "theta must lie in (1/3, 1] (near radius 1/theta in [1, 3) cells)");
@@ -770,6 +820,19 @@ int ot_fmm_plan_info(ot_fmm_plan P, ot_fmm_info *info)
 {
     if (!P || !info) return fail(OT_FMM_INVALID_ARGUMENT, "plan or info is NULL");
     *info = P->info;
+    info->leaf_chunks_forward = P->has_device ? P->dp.leaf_chunks[0] : 0;
+    info->leaf_chunks_adjoint = P->has_device ? P->dp.leaf_chunks[1] : 0;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_plan_set_leaf_chunks(ot_fmm_plan P, int forward, int adjoint)
+{
+    if (!P) return fail(OT_FMM_INVALID_ARGUMENT, "plan is NULL");
+    if (forward < 1 || forward > LEAF_MAX_CHUNKS || adjoint < 1 || adjoint > LEAF_MAX_CHUNKS)
+        return fail(OT_FMM_INVALID_ARGUMENT, "leaf chunk counts must lie in [1, 8]");
+    if (!P->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "plan was created with OT_FMM_HOST_ONLY");
+    P->dp.leaf_chunks[0] = forward;
+    P->dp.leaf_chunks[1] = adjoint;
     return OT_FMM_OK;
 }
 

@@ -41,6 +41,7 @@ constexpr int MAX_LEVELS = 8;                   // per-level arrays in the plan
 // untested and would need about 100 GB of plan memory.
 constexpr int MAX_DEPTH = 6;
 constexpr int WG = 256;                         // threads per workgroup (4 waves)
+constexpr int LEAF_MAX_CHUNKS = 8;              // waves per leaf block (stencil chunks)
 
 __host__ __device__ inline int off_index(int ox, int oy, int oz)
 {
@@ -99,6 +100,7 @@ struct DevPlan {
     const M2LDesc *mdesc; int n_mdesc;          // one per M2L workgroup
     int n_span; int span_top[MAX_LEVELS], span_n[MAX_LEVELS];   // tree passes over levels 0..L-2
     double e_leaf[NC];   // e_a(h/2, h/2, h/2): L2P shift magnitudes, leaf cell from its parent
+    int leaf_chunks[2];  // stencil chunks (waves per block) of the forward and adjoint leaf passes
     DevLevel lev[MAX_LEVELS];
 };
 
@@ -152,5 +154,7 @@ hipError_t m2l_blocks_per_cu(int fp32, int *n);   // resident M2L workgroups per
 hipError_t launch_l2l_span(const DevPlan &p, int span, hipStream_t s);
 hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s);
 hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s);
+// either leaf pass with an explicit chunk count (1 .. LEAF_MAX_CHUNKS)
+hipError_t launch_leaf_chunks(const DevPlan &p, int adj, int nchunk, double *out0, double *out1, hipStream_t s);
 
 }  // namespace otfmm

@@ -1035,16 +1035,24 @@ __device__ __forceinline__ void leaf_parent_local(const DevPlan &p, int Qx, int 
     l2l_apply(C, e, CR);
 }
 
+// Stencil chunks: the workgroup of block blk has nchunk waves; wave c sums
+// the c-th part of the parent-offset list (forward) or of the (plane, offset)
+// steps (adjoint) for the same 64 leaf parents, wave 0 also the L2P, and the
+// partial sums meet in LDS in the fixed order ((w1 + w2) + ...) + w0.  Small
+// trees get more waves this way; a given chunk count gives the same bits on
+// every call.
 template <bool ADJ>
-__global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__restrict__ Ks,
-                                             const char4 *__restrict__ plist, double *__restrict__ out0,
-                                             double *__restrict__ out1)
+__global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, const double *__restrict__ Ks,
+                                                              const char4 *__restrict__ plist,
+                                                              double *__restrict__ out0, double *__restrict__ out1,
+                                                              int nchunk)
 {
     const int npL = p.npL;
     const Block bs = block_shape(npL);
     const int nbx = npL / bs.bx, nby = npL / bs.by, nbz = npL / bs.bz;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x) * (WG / 64) + uniform(threadIdx.x >> 6);
-    if (blk >= nbx * nby * nbz) return;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    if (blk >= nbx * nby * nbz) return;             // the whole workgroup: no barrier is skipped
+    const int chunk = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
     const int Qy = ((blk / nbx) % nby) * bs.by + (lane / bs.bx) % bs.by;
@@ -1057,10 +1065,15 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
 
     constexpr int NA = ADJ ? 1 : 4;     // accumulators per sink child
     double acc[8][NA];
-    {
+    if (chunk == 0) {
         double C[NC];
         leaf_parent_local(p, Qx, Qy, Qz, C);
         leaf_l2p<ADJ, NA>(acc, C, p.e_leaf, std::make_integer_sequence<int, 8>{});
+    } else {
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) acc[b][a] = 0.0;
     }
 
     // The fetch of the next step is unconditional (the last step re-reads a
@@ -1082,9 +1095,10 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
                 dst[2 * c + 1] = v.y;
             }
         };
-        fetch(0, cur);
-        for (int pi = 0; pi < nP; ++pi) {
-            fetch(pi + 1 < nP ? pi + 1 : pi, nxt);
+        const int p0 = (int)((int64_t)chunk * nP / nchunk), p1 = (int)((int64_t)(chunk + 1) * nP / nchunk);
+        fetch(p0 < nP ? p0 : nP - 1, cur);
+        for (int pi = p0; pi < p1; ++pi) {
+            fetch(pi + 1 < p1 ? pi + 1 : pi, nxt);
             __builtin_amdgcn_sched_barrier(0);      // keep the prefetch ahead of the arithmetic
             const double *__restrict__ K = Ks + (size_t)pi * 27 * 4;
 #pragma unroll
@@ -1124,7 +1138,11 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
                 dst[2 * c + 1] = v.y;
             }
         };
-        int fj = 0, fi = 0;              // plane and entry of the next fetch
+        // this chunk's steps [s0, s1): multiples of four, as the ring needs
+        const int nst = 4 * nP;
+        auto bound = [&](int c) { return c >= nchunk ? nst : (int)((int64_t)c * nst / nchunk) & ~3; };
+        const int s0 = bound(chunk), s1 = bound(chunk + 1);
+        int fj = s0 / nP, fi = s0 % nP;  // plane and entry of the next fetch
         auto fetch_next = [&](double *dst) {    // wraps to the start after the last step
             fetch(fj, fi, dst);
             if (++fi == nP) {
@@ -1156,7 +1174,7 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
         __builtin_amdgcn_sched_barrier(0);
         fetch_next(r3);
         __builtin_amdgcn_sched_barrier(0);
-        for (int st = 0; st < 4 * nP; st += 4) {
+        for (int st = s0; st < s1; st += 4) {
             step(st, r0);
             fetch_next(r0);
             __builtin_amdgcn_sched_barrier(0);
@@ -1171,6 +1189,27 @@ __global__ __launch_bounds__(WG) void k_leaf(const DevPlan p, const double *__re
             __builtin_amdgcn_sched_barrier(0);
             asm volatile("" ::: "memory");      // no folding of the ring into loads at the loop head
         }
+    }
+
+    if (nchunk > 1) {
+        extern __shared__ double red[];     // [8 * NA][64] running sum of waves 1 .. c
+        for (int c = 1; c < nchunk; ++c) {
+            if (chunk == c) {
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+#pragma unroll
+                    for (int a = 0; a < NA; ++a) {
+                        double *r = &red[(b * NA + a) * 64 + lane];
+                        *r = (c == 1) ? acc[b][a] : *r + acc[b][a];
+                    }
+            }
+            __syncthreads();
+        }
+        if (chunk != 0) return;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) acc[b][a] += red[(b * NA + a) * 64 + lane];
     }
 
     const int sgx = Qx >> 2, sgy = Qy >> 2, sgz = Qz >> 2;
@@ -1271,22 +1310,31 @@ hipError_t launch_l2l_span(const DevPlan &p, int i, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s)
+// one workgroup of nchunk waves per block of 64 leaf parents
+hipError_t launch_leaf_chunks(const DevPlan &p, int adj, int nchunk, double *out0, double *out1, hipStream_t s)
 {
+    if (nchunk < 1 || nchunk > LEAF_MAX_CHUNKS) return hipErrorInvalidValue;
     const Block bs = block_shape(p.npL);
     const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
-    const unsigned grid = (unsigned)((((nblk + 3) / 4) + 7) / 8 * 8);   // whole rounds over the 8 XCDs
-    hipLaunchKernelGGL(k_leaf<false>, dim3(grid), dim3(WG), 0, s, p, p.Kst, p.plist_leaf, phi, g);
+    const unsigned grid = (unsigned)((nblk + 7) / 8 * 8);               // whole rounds over the 8 XCDs
+    const size_t lds = nchunk > 1 ? (size_t)8 * (adj ? 1 : 4) * 64 * sizeof(double) : 0;
+    if (adj)
+        hipLaunchKernelGGL(k_leaf<true>, dim3(grid), dim3(64 * nchunk), lds, s, p, p.Ksa, p.plist_leaf, out0,
+                           nullptr, nchunk);
+    else
+        hipLaunchKernelGGL(k_leaf<false>, dim3(grid), dim3(64 * nchunk), lds, s, p, p.Kst, p.plist_leaf, out0,
+                           out1, nchunk);
     return hipGetLastError();
+}
+
+hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s)
+{
+    return launch_leaf_chunks(p, 0, p.leaf_chunks[0], phi, g, s);
 }
 
 hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s)
 {
-    const Block bs = block_shape(p.npL);
-    const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
-    const unsigned grid = (unsigned)((((nblk + 3) / 4) + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_leaf<true>, dim3(grid), dim3(WG), 0, s, p, p.Ksa, p.plist_leaf, drho, nullptr);
-    return hipGetLastError();
+    return launch_leaf_chunks(p, 1, p.leaf_chunks[1], drho, nullptr, s);
 }
 
 }  // namespace otfmm

@@ -28,6 +28,7 @@ NO_DEVICE_STATE = -8
 FLAG_FP64 = 0
 FLAG_HOST_ONLY = 1
 FLAG_M2L_FP32 = 2
+FLAG_AUTOTUNE = 4
 
 NUM_PHASES = 8
 PHASES = ["upward_leaf", "m2m", "m2l", "l2l", "leaf", "upward_leaf_adj", "leaf_adj", "total"]
@@ -36,7 +37,8 @@ EXPORTS = ["ot_fmm_plan_create", "ot_fmm_forward", "ot_fmm_adjoint", "ot_fmm_pla
            "ot_fmm_destroy", "ot_fmm_status_string", "ot_fmm_last_error", "ot_fmm_timing_begin",
            "ot_fmm_timing_end", "ot_fmm_phase_name", "ot_fmm_timing_phases", "ot_fmm_batch_create",
            "ot_fmm_batch_forward", "ot_fmm_batch_adjoint", "ot_fmm_batch_capture_forward",
-           "ot_fmm_batch_capture_adjoint", "ot_fmm_graph_launch", "ot_fmm_graph_destroy", "ot_fmm_batch_destroy"]
+           "ot_fmm_batch_capture_adjoint", "ot_fmm_graph_launch", "ot_fmm_graph_destroy", "ot_fmm_batch_destroy",
+           "ot_fmm_plan_set_leaf_chunks"]
 
 
 class OTFMMError(RuntimeError):
@@ -56,7 +58,8 @@ class _Info(C.Structure):
                 ("n_nodes", C.c_int64), ("n_leaf_nodes", C.c_int64), ("n_leaf_cells", C.c_int64),
                 ("p2p_pairs", C.c_int64), ("m2l_pairs", C.c_int64), ("m2l_pairs_level", C.c_int64 * 16),
                 ("flops_forward", C.c_double), ("flops_adjoint", C.c_double),
-                ("bytes_forward", C.c_double), ("bytes_adjoint", C.c_double), ("device_bytes", C.c_size_t)]
+                ("bytes_forward", C.c_double), ("bytes_adjoint", C.c_double), ("device_bytes", C.c_size_t),
+                ("leaf_chunks_forward", C.c_int32), ("leaf_chunks_adjoint", C.c_int32)]
 
 
 class _Timing(C.Structure):
@@ -98,6 +101,8 @@ def load_library():
     lib.ot_fmm_phase_name.restype = C.c_char_p
     lib.ot_fmm_timing_phases.argtypes = [vp, C.c_uint32]
     lib.ot_fmm_timing_phases.restype = C.c_int
+    lib.ot_fmm_plan_set_leaf_chunks.argtypes = [vp, C.c_int, C.c_int]
+    lib.ot_fmm_plan_set_leaf_chunks.restype = C.c_int
     pp = C.POINTER(vp)
     lib.ot_fmm_batch_create.argtypes = [pp, C.c_int, C.c_int, C.POINTER(vp)]
     lib.ot_fmm_batch_create.restype = C.c_int
@@ -128,10 +133,11 @@ class Plan:
 
     All device memory is allocated here, on the current device; forward and
     adjoint only enqueue kernels on the current torch stream.  m2l_fp32 runs
-    the M2L in FP32 with FP64 accumulation (OT_FMM_M2L_FP32)."""
+    the M2L in FP32 with FP64 accumulation (OT_FMM_M2L_FP32); autotune times
+    the leaf passes' stencil chunk counts at creation (OT_FMM_AUTOTUNE)."""
 
     def __init__(self, layout, theta: float = 0.4, order: int = 3, host_only: bool = False,
-                 m2l_fp32: bool = False):
+                 m2l_fp32: bool = False, autotune: bool = False):
         lib = load_library()
         self._keep = [np.ascontiguousarray(layout.level, dtype=np.int32),
                       np.ascontiguousarray(layout.coord, dtype=np.int32).reshape(-1),
@@ -148,7 +154,8 @@ class Plan:
         L.origin = (C.c_double * 3)(*[float(x) for x in layout.origin])
         L.G = float(layout.G)
         self._handle = C.c_void_p()
-        flags = (FLAG_HOST_ONLY if host_only else FLAG_FP64) | (FLAG_M2L_FP32 if m2l_fp32 else 0)
+        flags = ((FLAG_HOST_ONLY if host_only else FLAG_FP64) | (FLAG_M2L_FP32 if m2l_fp32 else 0)
+                 | (FLAG_AUTOTUNE if autotune else 0))
         _check(lib.ot_fmm_plan_create(C.byref(L), float(theta), int(order), flags, C.byref(self._handle)))
         self._keep = None
         self.layout = layout
@@ -176,6 +183,10 @@ class Plan:
         d = {k: getattr(inf, k) for k, _ in _Info._fields_}
         d["m2l_pairs_level"] = list(inf.m2l_pairs_level)[: max(inf.depth, 0)]
         return d
+
+    def set_leaf_chunks(self, forward: int, adjoint: int):
+        """Stencil chunk counts (1..8) of the forward and adjoint leaf passes."""
+        _check(load_library().ot_fmm_plan_set_leaf_chunks(self._handle, int(forward), int(adjoint)))
 
     # ------------------------------------------------------------------ calls
     def _stream(self):

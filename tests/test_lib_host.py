@@ -81,6 +81,10 @@ def test_host_only_plan_refuses_compute():
     rc = lib.ot_fmm_adjoint(p._handle, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None)
     assert rc == fmm.NO_DEVICE_STATE
     assert lib.ot_fmm_timing_begin(p._handle, 4) == fmm.NO_DEVICE_STATE
+    assert lib.ot_fmm_plan_set_leaf_chunks(p._handle, 2, 2) == fmm.NO_DEVICE_STATE
+    for bad in ((0, 1), (1, 9), (-1, 4)):
+        assert lib.ot_fmm_plan_set_leaf_chunks(p._handle, *bad) == fmm.INVALID_ARGUMENT
+    assert lib.ot_fmm_plan_set_leaf_chunks(None, 1, 1) == fmm.INVALID_ARGUMENT
 
 
 def test_null_arguments():
@@ -127,8 +131,8 @@ def test_batch_argument_errors():
 
 
 def test_flags():
-    """OT_FMM_M2L_FP32 is accepted (and changes no host-side count); unknown
-    flag bits are rejected."""
+    """OT_FMM_M2L_FP32 and OT_FMM_AUTOTUNE are accepted (and change no
+    host-side count); unknown flag bits are rejected."""
     import ctypes as C
     lay = W.uniform_layout(2)
     a = fmm.Plan(lay, host_only=True).info()
@@ -147,11 +151,16 @@ def test_flags():
     L.origin = (C.c_double * 3)(0.0, 0.0, 0.0)
     L.G = 1.0
     h = C.c_void_p()
-    for bad in (1 << 2, 1 << 31):
+    for bad in (1 << 3, 1 << 31):
         assert lib.ot_fmm_plan_create(C.byref(L), 0.4, 3, fmm.FLAG_HOST_ONLY | bad, C.byref(h)) == fmm.INVALID_ARGUMENT
         assert h.value is None
-    assert lib.ot_fmm_plan_create(C.byref(L), 0.4, 3, fmm.FLAG_HOST_ONLY | fmm.FLAG_M2L_FP32, C.byref(h)) == fmm.OK
-    lib.ot_fmm_destroy(h)
+    for good in (fmm.FLAG_M2L_FP32, fmm.FLAG_AUTOTUNE, fmm.FLAG_M2L_FP32 | fmm.FLAG_AUTOTUNE):
+        assert lib.ot_fmm_plan_create(C.byref(L), 0.4, 3, fmm.FLAG_HOST_ONLY | good, C.byref(h)) == fmm.OK
+        lib.ot_fmm_destroy(h)
+        h = C.c_void_p()
+    # a host-only plan has no leaf passes to tune: it reports no chunk counts
+    info = fmm.Plan(lay, host_only=True, autotune=True).info()
+    assert info["leaf_chunks_forward"] == 0 and info["leaf_chunks_adjoint"] == 0
 
 
 def _expect(status, layout, theta=0.4, order=3):
