@@ -417,13 +417,31 @@ typedef __attribute__((address_space(3))) void lvoid;       // LDS
 // loads into LDS included, are complete
 constexpr int WAIT_VMCNT0 = 0x0F70;
 
-// C[k] += sum over the pieces of cp[(piece * NC + k) * cs]; all loads of a
-// piece are issued before the first add
+// C[k] += sum over the pieces of cp[(piece * NC + k) * cs], in piece order.
+// The loads of U pieces are issued before the first of their adds, so a
+// cell with many pieces waits U times less often.
+template <int U>
 __device__ __forceinline__ void add_pieces(double *C, const double *cp, int64_t cs, int maxp)
 {
-    for (int piece = 0; piece < maxp; ++piece) {
+    int piece = 0;
+    for (; piece + U <= maxp; piece += U) {
+        double t[U][NC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double *pc = cp + (piece + u) * NC * cs;
+            asm volatile("" : "+v"(pc));     // one address per piece, not one induction pointer per component
+            const gdouble *g = (const gdouble *)pc;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) t[u][k] = g[k * cs];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) C[k] += t[u][k];
+    }
+    for (; piece < maxp; ++piece) {
         const double *pc = cp + piece * NC * cs;
-        asm volatile("" : "+v"(pc));     // one address per piece, not one induction pointer per component
+        asm volatile("" : "+v"(pc));
         const gdouble *g = (const gdouble *)pc;
         double t[NC];
 #pragma unroll
@@ -900,7 +918,7 @@ __global__ __launch_bounds__(L2L_SPAN_WG) void k_l2l_span(const DevPlan p, int l
         const int64_t np = D.np;
         np3 = np * np * np;
         q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
-        add_pieces(C, D.Cp + bs * np3 + q, 8 * np3, D.maxp);
+        add_pieces<4>(C, D.Cp + bs * np3 + q, 8 * np3, D.maxp);
     }
     for (int st = 0; st < nlev; ++st) {
         if (act && j == st) {
@@ -1020,7 +1038,7 @@ __device__ __forceinline__ void leaf_parent_local(const DevPlan &p, int Qx, int 
     const int bQ = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
     const int64_t nq = D.np, nq3 = nq * nq * nq;
     const int64_t q = ((int64_t)(Qz >> 1) * nq + (Qy >> 1)) * nq + (Qx >> 1);
-    add_pieces(C, D.Cp + bQ * nq3 + q, 8 * nq3, D.maxp);
+    add_pieces<1>(C, D.Cp + bQ * nq3 + q, 8 * nq3, D.maxp);
     if (p.L < 2) return;
     const DevLevel &Dp = p.lev[p.L - 2];
     const int Rx = Qx >> 1, Ry = Qy >> 1, Rz = Qz >> 1;
