@@ -141,3 +141,44 @@ def test_capture_refused_while_timing(trees):
     finally:
         trees[0]["plan"].timing_end()
         b.close()
+
+
+def test_batch_mixed_depths_and_precisions():
+    """Depths 0, 1 and 5 (no M2L, one level, two M2M spans) with one FP32-M2L
+    plan: the shared M2L launch takes each precision group apart, and every
+    plan still gives its single call's bits."""
+    rng = np.random.default_rng(900)
+    specs = [(0, False), (1, False), (5, False), (2, True), (3, False)]
+    plans, rhos, ws, us = [], [], [], []
+    for L, f32 in specs:
+        n = 8 << L
+        lay = W.uniform_layout(L)
+        plans.append(fmm.Plan(lay, m2l_fp32=f32))
+        dev = lambda a, lay=lay: torch.from_numpy(lay.dense_to_layout(np.ascontiguousarray(a))).cuda()  # noqa: E731
+        rhos.append(dev(rng.uniform(0.0, 1.0, (n, n, n))))
+        ws.append(dev(rng.standard_normal((n, n, n))))
+        us.append(dev(rng.standard_normal((3, n, n, n))).reshape(-1))
+    say("mixed batch:", specs)
+    ref = []
+    for p, r, w, u in zip(plans, rhos, ws, us):
+        phi, g = p.forward(r)
+        ref.append((phi, g.reshape(-1), p.adjoint(w, u)))
+    torch.cuda.synchronize()
+    b = fmm.Batch(plans, n_streams=3)
+    phis = [torch.empty_like(r) for r in rhos]
+    gs = [torch.empty(3 * r.numel(), dtype=torch.float64, device="cuda") for r in rhos]
+    drhos = [torch.empty_like(r) for r in rhos]
+    b.forward_into(rhos, phis, gs)
+    b.adjoint_into(ws, us, drhos)
+    torch.cuda.synchronize()
+    for i, (phi, g, dr) in enumerate(ref):
+        assert torch.equal(phis[i], phi) and torch.equal(gs[i], g) and torch.equal(drhos[i], dr), specs[i]
+    gf = b.capture_forward(rhos, phis, gs)
+    for x in phis + gs:
+        x.fill_(float("nan"))
+    gf.launch()
+    torch.cuda.synchronize()
+    for i, (phi, g, _) in enumerate(ref):
+        assert torch.equal(phis[i], phi) and torch.equal(gs[i], g), specs[i]
+    gf.close()
+    b.close()
