@@ -77,7 +77,7 @@ extern "C" {
                                         (1, 2, 4 or 8 waves per block of 64 leaf
                                         parents) by timing them at plan creation;
                                         without it the count follows from the tree
-                                        size (at least ~2048 waves per launch).
+                                        size (at least ~16384 waves per launch).
                                         Results of different counts agree to
                                         rounding; a plan keeps its counts, so its
                                         calls repeat bit for bit. */

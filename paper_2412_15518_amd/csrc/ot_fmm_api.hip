@@ -561,11 +561,14 @@ int setup_device(ot_fmm_plan P)
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }
-    // stencil chunks of the leaf passes: enough waves for at least ~2048 per
-    // launch (two per SIMD), at most LEAF_MAX_CHUNKS per block
+    // stencil chunks of the leaf passes: the smallest power of two that gives
+    // a launch at least 16384 waves (four rounds of the 4096 wave slots the
+    // leaf kernels' registers leave), at most LEAF_MAX_CHUNKS per block.  The
+    // timing tuner picks the same counts at depths 1..4 (8, 8, 8, 4) and at
+    // depth 5 (1) for the adjoint.
     const int64_t nblk = (int64_t)d.npL * d.npL * d.npL / 64;
     int c = 1;
-    while (c < LEAF_MAX_CHUNKS && nblk * c < 2048) c *= 2;
+    while (c < LEAF_MAX_CHUNKS && nblk * c < 16384) c *= 2;
     d.leaf_chunks[0] = d.leaf_chunks[1] = c;
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize after plan setup");

@@ -87,7 +87,10 @@ def test_autotuned_plan_is_valid_and_repeats():
     assert normwise(a[0].cpu().numpy(), c[0].cpu().numpy()) < 1e-14
 
 
-def test_large_tree_keeps_one_chunk():
-    """128^3 has 4096 leaf blocks: the size rule keeps one wave per block."""
-    inf = fmm.Plan(W.uniform_layout(4)).info()
-    assert inf["leaf_chunks_forward"] == 1 and inf["leaf_chunks_adjoint"] == 1
+def test_size_rule():
+    """The size rule: the smallest power of two giving >= 16384 waves per leaf
+    launch, at most 8 -- 8 chunks up to 64^3, 4 at 128^3 (4096 leaf blocks),
+    1 at 256^3 (32768 blocks)."""
+    for L, c in ((1, 8), (3, 8), (4, 4), (5, 1)):
+        inf = fmm.Plan(W.uniform_layout(L)).info()
+        assert inf["leaf_chunks_forward"] == c and inf["leaf_chunks_adjoint"] == c, (L, inf["leaf_chunks_forward"])
