@@ -193,6 +193,44 @@ def test_depth5_two_tree_spans():
     assert np.abs(dr[z] - do[z]).max() / np.abs(do[z]).max() < TOL
 
 
+def test_depth6_largest_supported_tree():
+    """512^3 (depth 6, 134M cells), the deepest tree a plan accepts: the
+    forward on sampled sinks against the oracle, and the adjoint through the
+    dot-product identity on the whole grid."""
+    n, L = 512, 6
+    rng = np.random.default_rng(606)
+    lay = W.uniform_layout(L)
+    plan = fmm.Plan(lay)
+    inf = plan.info()
+    say(f"512^3 plan: {inf['device_bytes'] / 2**30:.1f} GiB of device memory")
+    assert inf["depth"] == L
+    rho = rng.uniform(0.0, 1.0, (n, n, n))
+    rd = to_dev(lay, rho)
+    phi_d, g_d = plan.forward(rd)
+    wd = torch.randn(n ** 3, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(61))
+    ud = torch.randn(3 * n ** 3, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(62))
+    dr_d = plan.adjoint(wd, ud)
+    torch.cuda.synchronize()
+    lhs = float((wd * phi_d).sum() + (ud.reshape(3, -1) * g_d).sum())
+    rhs = float((dr_d * rd).sum())
+    scale = float((wd * phi_d).abs().sum() + (ud.reshape(3, -1) * g_d).abs().sum())
+    say(f"dot-product identity: {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) / scale < 1e-12
+    del wd, ud, dr_d, rd
+    phi = lay.layout_to_dense(phi_d.cpu().numpy())
+    g = lay.layout_to_dense(g_d.cpu().numpy())
+    del phi_d, g_d
+    sinks = np.concatenate([rng.choice(n ** 3, 64, replace=False),
+                            [0, n - 1, n ** 3 - 1, (256 * n + 255) * n + 256]]).astype(np.int64)
+    say("oracle sinks", sinks.size)
+    po, go = O.fmm_sinks(rho, sinks)
+    e_phi = np.abs(phi.reshape(-1)[sinks] - po).max() / np.abs(phi).max()
+    gg = g.reshape(3, -1)[:, sinks]
+    e_g = np.sqrt(((gg - go) ** 2).sum(0)).max() / np.sqrt((g ** 2).sum(0)).max()
+    say(f"sinks: phi {e_phi:.2e} g {e_g:.2e}")
+    assert e_phi < TOL and e_g < TOL
+
+
 def test_deterministic_bitwise():
     cfg = W.cfg5_lognormal()
     lay = W.uniform_layout(cfg["L"])
