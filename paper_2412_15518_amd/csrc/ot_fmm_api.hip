@@ -285,54 +285,82 @@ void build_tables(ot_fmm_plan P)
 
 }
 
+// Whether M2L unit (block blk, parent offset P) of a level with np parents
+// per axis has a source in the domain: the block's parents shifted by P
+// overlap [0, np) on every axis.  The blocks are those of the kernels: 64
+// parents, bx * by * bz, numbered x fastest.
+bool unit_has_sources(int np, int blk, char4 P)
+{
+    const int bx = std::min(np, 64), by = std::min(np, 64 / bx), bz = 64 / (bx * by);
+    const int nbx = np / bx, nby = np / by;
+    const int x0 = (blk % nbx) * bx, y0 = ((blk / nbx) % nby) * by, z0 = (blk / (nbx * nby)) * bz;
+    auto overlap = [np](int a0, int n, int o) { return a0 + o < np && a0 + n - 1 + o >= 0; };
+    return overlap(x0, bx, P.x) && overlap(y0, by, P.y) && overlap(z0, bz, P.z);
+}
+
 // Cut each level's M2L units into runs, G workgroups in all, in proportion
-// to the level's units (at least one run per level), and record per level how
-// many partial sums a block can receive.
+// to the level's units with sources in the domain (at least one run per
+// level); runs are balanced in those units and skip the others.  Records
+// per level the unit mask and how many partial sums a block can receive.
 void build_m2l_schedule(ot_fmm_plan P, int G)
 {
     P->mdesc.clear();
     const int L = P->L;
-    for (int l = 0; l < MAX_LEVELS; ++l) P->dp.lev[l].maxp = 0;
+    for (int l = 0; l < MAX_LEVELS; ++l) {
+        P->dp.lev[l].maxp = 0;
+        P->umask[l].clear();
+    }
     if (L < 1) return;
-    std::vector<int64_t> U(L);
-    int64_t Utot = 0;
+    std::vector<std::vector<int64_t>> pos(L);     // each level's computed units, in order
+    std::vector<int64_t> U(L), V(L);
+    int64_t Vtot = 0;
     for (int l = 0; l < L; ++l) {
-        const int64_t nblocks = (int64_t)(4 << l) * (4 << l) * (4 << l) / 64;
-        const int nP = (l == 0) ? (int)P->plist_cube.size() : (int)P->plist_near.size();
-        U[l] = nblocks * nP;
-        Utot += U[l];
+        const int np = 4 << l;
+        const std::vector<char4> &pl = (l == 0) ? P->plist_cube : P->plist_near;
+        const int nP = (int)pl.size();
+        U[l] = (int64_t)np * np * np / 64 * nP;
+        P->umask[l].assign((size_t)((U[l] + 31) / 32), 0u);
+        for (int64_t u = 0; u < U[l]; ++u)
+            if (unit_has_sources(np, (int)(u / nP), pl[u % nP])) {
+                P->umask[l][u >> 5] |= 1u << (u & 31);
+                pos[l].push_back(u);
+            }
+        V[l] = (int64_t)pos[l].size();
+        Vtot += V[l];
     }
     std::vector<int> Gl(L);
     int used = 0;
     for (int l = 0; l < L; ++l) {
         // at least one run per level, and runs of at least 8 units (32 tiles)
-        Gl[l] = (int)std::max<int64_t>(1, std::min<int64_t>(U[l] / 8, (int64_t)G * U[l] / Utot));
+        Gl[l] = (int)std::max<int64_t>(1, std::min<int64_t>(V[l] / 8, (int64_t)G * V[l] / Vtot));
         used += Gl[l];
     }
     // hand any remainder to the deepest level
-    if (used < G) Gl[L - 1] = (int)std::max<int64_t>(1, std::min<int64_t>(U[L - 1] / 8, Gl[L - 1] + (G - used)));
+    if (used < G) Gl[L - 1] = (int)std::max<int64_t>(1, std::min<int64_t>(V[L - 1] / 8, Gl[L - 1] + (G - used)));
     for (int l = L - 1; l >= 0; --l) {
         const int nP = (l == 0) ? (int)P->plist_cube.size() : (int)P->plist_near.size();
-        const int64_t Ul = U[l];
         const int g = Gl[l];
-        auto run_of = [&](int64_t u) {        // run of this level holding unit u
-            int r = (int)(u * g / Ul);
-            while (r + 1 < g && (int64_t)(r + 1) * Ul / g <= u) ++r;
-            while (r > 0 && (int64_t)r * Ul / g > u) --r;
-            return r;
+        // run r covers raw units [b[r], b[r + 1]): from its first computed unit
+        // (run 0 from unit 0) up to the next run's
+        std::vector<int64_t> b(g + 1);
+        for (int r = 0; r < g; ++r) b[r] = (r == 0) ? 0 : pos[l][(size_t)((int64_t)r * V[l] / g)];
+        b[g] = U[l];
+        auto run_of = [&](int64_t u) {        // run of this level whose range holds unit u
+            return (int)(std::upper_bound(b.begin(), b.end(), u) - b.begin()) - 1;
         };
         for (int r = 0; r < g; ++r) {
             M2LDesc d{};
             d.level = l;
-            d.ubeg = (int)((int64_t)r * Ul / g);
-            d.uend = (int)((int64_t)(r + 1) * Ul / g);
+            d.ubeg = (int)b[r];
+            d.uend = (int)b[r + 1];
+            d.nvalid = (int)((int64_t)(r + 1) * V[l] / g - (int64_t)r * V[l] / g);
             const int64_t first = (int64_t)(d.ubeg / nP) * nP;
             d.piece0 = (d.ubeg == first) ? 0 : r - run_of(first);
             P->mdesc.push_back(d);
         }
         int maxp = 0;
-        for (int64_t b = 0; b < Ul / nP; ++b)
-            maxp = std::max(maxp, run_of(b * nP + nP - 1) - run_of(b * nP) + 1);
+        for (int64_t blk = 0; blk < U[l] / nP; ++blk)
+            maxp = std::max(maxp, run_of(blk * nP + nP - 1) - run_of(blk * nP) + 1);
         P->dp.lev[l].maxp = maxp;
     }
 }
@@ -558,6 +586,7 @@ int setup_device(ot_fmm_plan P)
             return rc;
         }
         if (l < L - 1 && (rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
+        if ((rc = dev_upload(P, &v.umask, P->umask[l]))) return rc;
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }

@@ -61,6 +61,7 @@ struct DevLevel {
     float *M32;      // [NR/4][8][pp^3][4] the same in FP32 (FP32 M2L; else null)
     double *C;       // [NC][8][np^3] local coefficients (final); null at level L-1
     double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
+    const uint32_t *umask;   // bit u: M2L unit u (block u / nP, offset u % nP) has a source in the domain
 };
 
 // M2L work: a block = 64 sink parents of one level (bx*by*bz parents, lane =
@@ -72,10 +73,14 @@ struct DevLevel {
 // sums, pieces 0..k-1 of the level's Cp: the run holding the block's first
 // unit writes piece 0, the next run piece 1, and so on.  Consumers add the
 // pieces in a fixed order, so the result does not depend on timing.
+// A unit whose 64 sources all lie outside the domain (in the zero halo)
+// contributes nothing: the runs skip it, and are cut at equal counts of the
+// other units.  A piece whose run skips all of its block's units stays zero.
 struct M2LDesc {
     int level;
     int ubeg, uend;
     int piece0;      // piece of the run's first (possibly partial) block
+    int nvalid;      // units of [ubeg, uend) with a source in the domain (the only ones computed)
 };
 
 struct DevPlan {
@@ -132,6 +137,7 @@ struct ot_fmm_plan_s {
     std::vector<int32_t> leaf_slot;
     std::vector<char4> plist_near, plist_cube;
     std::vector<otfmm::M2LDesc> mdesc;
+    std::vector<uint32_t> umask[otfmm::MAX_LEVELS];   // M2L units with sources in the domain, per level
     std::vector<double> Ktab, Kst, Ksa, Dtab;
     std::vector<float> Dtab32;
     ot_fmm_info info{};

@@ -561,6 +561,16 @@ constexpr int M2L_TBP = 2;                       // source children per tile
 // it changes.
 constexpr int M2L_WG = 512;                       // 8 waves, one per sink child
 
+typedef const __attribute__((address_space(4))) uint32_t cuint32;
+
+// bit u of a level's unit mask: unit u has a source in the domain.  The mask
+// is never written by a kernel; read through the constant address space, its
+// words arrive by scalar loads.
+__device__ __forceinline__ bool unit_computed(const uint32_t *mask, int u)
+{
+    return (((const cuint32 *)mask)[u >> 5] >> (u & 31)) & 1u;
+}
+
 template <int PAIR, int... I>
 __device__ __forceinline__ void m2l1_pair(double *C, const double *D, double2 m, std::integer_sequence<int, I...>)
 {
@@ -635,12 +645,23 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
     constexpr int TPP = 8 / M2L_TBP;                // tiles per unit
     constexpr int ROWS = M2L_TBP * NR / 2;          // 16-byte rows of 64 lanes per tile
     static_assert(ROWS % 8 == 0, "each wave loads the same number of rows");
-    const int ntiles = (d.uend - d.ubeg) * TPP;
+    const int ntiles = d.nvalid * TPP;
+    if (ntiles == 0) return;                       // the whole workgroup
 
     // fetch cursor: block fb, parent offset fi, tile ft.  Wave w loads rows
     // r = w + 8 j of the next tile (component pair r % 8 of tile child r / 8)
     // straight from global memory into LDS, 16 bytes per lane.
+    // the units of the run that have sources in the domain, in order
+    auto next_unit = [&](int &blk, int &i) {
+        do {
+            if (++i == nP) {
+                i = 0;
+                ++blk;
+            }
+        } while (!unit_computed(D.umask, blk * nP + i));
+    };
     int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
+    if (!unit_computed(D.umask, d.ubeg)) next_unit(fb, fi);
     int fmq = lane_mq(fb);
     auto fetch = [&](double2 (*t)[NR / 2][64]) {
         const char4 P = plist[fi];
@@ -655,9 +676,10 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
     // those of every wave
     auto loads_done = [&]() { __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0); };
 
-    // compute cursor
+    // compute cursor; the run's first raw block takes piece piece0, a block
+    // that starts inside the run piece 0
     int cb = fb, ci = fi, ct = 0;
-    int piece = d.piece0;
+    int piece = (cb == d.ubeg / nP) ? d.piece0 : 0;
 
     double C[NR];
 #pragma unroll
@@ -677,10 +699,9 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
         if (k + 1 < ntiles) {
             if (++ft == TPP) {
                 ft = 0;
-                if (++fi == nP) {
-                    fi = 0;
-                    fmq = lane_mq(++fb);
-                }
+                const int ob = fb;
+                next_unit(fb, fi);
+                if (fb != ob) fmq = lane_mq(fb);
             }
             fetch(nxt);
         }
@@ -698,14 +719,16 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
             for (int q = 0; q < NC; ++q) Dv[q] = Dr[q];
             m2l1_child(C, Dv, &cur[i][0][0], lane);
         }
-        if (++ct == TPP) {
+        if (++ct == TPP && k + 1 < ntiles) {
             ct = 0;
-            if (++ci == nP) {                   // block complete: store its piece
+            int nb = cb, ni = ci;
+            next_unit(nb, ni);
+            if (nb != cb) {                     // block done in this run: store its piece
                 flush();
                 piece = 0;
-                ci = 0;
-                ++cb;
             }
+            cb = nb;
+            ci = ni;
         }
         loads_done();
         __syncthreads();
@@ -718,7 +741,7 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
         step(k, tile0, tile1);
         if (k + 1 < ntiles) step(k + 1, tile1, tile0);
     }
-    if (ci != 0 || ct != 0) flush();            // run ended inside a block
+    flush();                                    // the run's last block
 }
 
 // M2L in FP32 (plan flag OT_FMM_M2L_FP32).  The schedule, the work mapping
@@ -796,11 +819,21 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
         return ((qz + hp) * pp + (qy + hp)) * pp + (qx + hp);
     };
     constexpr int TPP = 8 / M2L_TBP;                // tiles per unit
-    const int ntiles = (d.uend - d.ubeg) * TPP;
+    const int ntiles = d.nvalid * TPP;
+    if (ntiles == 0) return;                       // the whole workgroup
 
     // fetch cursor as in k_m2l; wave w loads quad row w of the next tile
     // (tile child w / 4, reduced components 4 (w % 4) .. + 3) into LDS
+    auto next_unit = [&](int &blk, int &i) {       // as in k_m2l
+        do {
+            if (++i == nP) {
+                i = 0;
+                ++blk;
+            }
+        } while (!unit_computed(D.umask, blk * nP + i));
+    };
     int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
+    if (!unit_computed(D.umask, d.ubeg)) next_unit(fb, fi);
     int fmq = lane_mq(fb);
     const int ti = b / (NR / 4), tq = b % (NR / 4);
     auto fetch = [&](float4 (*t)[NR / 4][64]) {
@@ -811,7 +844,7 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
     auto loads_done = [&]() { __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0); };
 
     int cb = fb, ci = fi, ct = 0;
-    int piece = d.piece0;
+    int piece = (cb == d.ubeg / nP) ? d.piece0 : 0;
 
     double C[NR];           // FP64 accumulators of the block
     float Cf[NR];           // FP32 sum of the current parent offset
@@ -842,10 +875,9 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
         if (k + 1 < ntiles) {
             if (++ft == TPP) {
                 ft = 0;
-                if (++fi == nP) {
-                    fi = 0;
-                    fmq = lane_mq(++fb);
-                }
+                const int ob = fb;
+                next_unit(fb, fi);
+                if (fb != ob) fmq = lane_mq(fb);
             }
             fetch(nxt);
         }
@@ -866,11 +898,15 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
         if (++ct == TPP) {
             ct = 0;
             fold();                             // one parent offset done
-            if (++ci == nP) {                   // block complete: store its piece
-                flush();
-                piece = 0;
-                ci = 0;
-                ++cb;
+            if (k + 1 < ntiles) {
+                int nb = cb, ni = ci;
+                next_unit(nb, ni);
+                if (nb != cb) {                 // block done in this run: store its piece
+                    flush();
+                    piece = 0;
+                }
+                cb = nb;
+                ci = ni;
             }
         }
         loads_done();
@@ -884,7 +920,7 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
         step(k, tile0, tile1);
         if (k + 1 < ntiles) step(k + 1, tile1, tile0);
     }
-    if (ci != 0 || ct != 0) flush();            // run ended inside a block
+    flush();                                    // the run's last block
 }
 
 // L2L over a span, top level first.  Thread groups: t = 0 the cell A,
