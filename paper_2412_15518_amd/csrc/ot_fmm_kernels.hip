@@ -1095,6 +1095,10 @@ __device__ __forceinline__ void leaf_parent_local(const DevPlan &p, int Qx, int 
 // partial sums meet in LDS in the fixed order ((w1 + w2) + ...) + w0.  Small
 // trees get more waves this way; a given chunk count gives the same bits on
 // every call.
+// steps of the P2P loop that wave 0's prologue (the pieces, the L2L from the
+// parent and the L2P) is worth: wave 0 takes that many fewer steps (forward
+// steps of 256 FMA, adjoint steps of 64)
+constexpr int LEAF_LEAD = 4, LEAF_LEAD_ADJ = 16;
 template <bool ADJ>
 __global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, const double *__restrict__ Ks,
                                                               const char4 *__restrict__ plist,
@@ -1149,7 +1153,15 @@ __global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, 
                 dst[2 * c + 1] = v.y;
             }
         };
-        const int p0 = (int)((int64_t)chunk * nP / nchunk), p1 = (int)((int64_t)(chunk + 1) * nP / nchunk);
+        // wave 0 also forms the local expansion and its L2P: it takes LEAF_LEAD
+        // fewer steps, the others share them
+        auto pbound = [&](int c) {
+            if (c == 0) return 0;
+            if (c >= nchunk) return nP;
+            const int v = (int)((int64_t)c * (nP + LEAF_LEAD) / nchunk) - LEAF_LEAD;
+            return v < 0 ? 0 : v;
+        };
+        const int p0 = pbound(chunk), p1 = pbound(chunk + 1);
         fetch(p0 < nP ? p0 : nP - 1, cur);
         for (int pi = p0; pi < p1; ++pi) {
             fetch(pi + 1 < p1 ? pi + 1 : pi, nxt);
@@ -1194,7 +1206,12 @@ __global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, 
         };
         // this chunk's steps [s0, s1): multiples of four, as the ring needs
         const int nst = 4 * nP;
-        auto bound = [&](int c) { return c >= nchunk ? nst : (int)((int64_t)c * nst / nchunk) & ~3; };
+        auto bound = [&](int c) {
+            if (c == 0) return 0;
+            if (c >= nchunk) return nst;
+            const int v = ((int)((int64_t)c * (nst + LEAF_LEAD_ADJ) / nchunk) - LEAF_LEAD_ADJ) & ~3;
+            return v < 0 ? 0 : v;
+        };
         const int s0 = bound(chunk), s1 = bound(chunk + 1);
         int fj = s0 / nP, fi = s0 % nP;  // plane and entry of the next fetch
         auto fetch_next = [&](double *dst) {    // wraps to the start after the last step
