@@ -22,6 +22,8 @@ _lib = None
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 _i64p = C.POINTER(C.c_int64)
+_i32p = C.POINTER(C.c_int32)
+_u8p = C.POINTER(C.c_uint8)
 
 
 def _load():
@@ -48,6 +50,11 @@ def _load():
     lib.oracle_moments.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, _dp]
     lib.oracle_pair_counts.argtypes = [C.c_int, C.c_double, _i64p, _i64p]
     lib.oracle_pair_counts_slab.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _i64p, _i64p]
+    _tree = [C.c_int64, _i32p, _i32p, _u8p]
+    lib.oracle_amr_sinks.argtypes = _tree + [C.c_int, C.c_double, C.c_double, C.c_double, _dp,
+                                             C.c_int64, _i64p, _dp, _dp]
+    lib.oracle_amr_direct.argtypes = _tree + [C.c_double, C.c_double, _dp, C.c_int64, _i64p, _dp, _dp]
+    lib.oracle_amr_cover.argtypes = _tree + [C.c_double, C.c_int64, _i32p]
     _lib = lib
     return lib
 
@@ -168,3 +175,54 @@ def pair_counts(L, theta=0.4, zslab=None):
     _check(_load().oracle_pair_counts_slab(L, theta, zlo, zhi, C.byref(p2p), m2l.ctypes.data_as(_i64p)),
            "pair_counts")
     return int(p2p.value), m2l
+
+
+# --------------------------------------------------------------------------
+# adaptive octrees: layouts as in the library (level, coord [n, 3], is_leaf),
+# leaf-cell arrays in layout order (512 per leaf sub-grid, x fastest)
+# --------------------------------------------------------------------------
+def _tree_args(layout):
+    lvl = np.ascontiguousarray(layout.level, dtype=np.int32)
+    crd = np.ascontiguousarray(layout.coord, dtype=np.int32)
+    leaf = np.ascontiguousarray(layout.is_leaf, dtype=np.uint8)
+    keep = (lvl, crd, leaf)
+    return keep, [lvl.shape[0], lvl.ctypes.data_as(_i32p), crd.ctypes.data_as(_i32p), leaf.ctypes.data_as(_u8p)]
+
+
+def _sinks(layout, sinks):
+    n = int(layout.is_leaf.sum()) * 512
+    return np.arange(n, dtype=np.int64) if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+
+
+def amr_fmm_sinks(layout, rho, sinks=None, p=3, theta=0.4, G=None):
+    """FMM forward on an adaptive octree at the given leaf cells (all when
+    None): (phi [k], g [3, k]).  Raises on trees that are not 2:1 balanced."""
+    keep, t = _tree_args(layout)
+    rho = _c64(rho)
+    s = _sinks(layout, sinks)
+    phi = np.zeros(s.size); g = np.zeros((3, s.size))
+    G = layout.G if G is None else G
+    rc = _load().oracle_amr_sinks(*t, p, theta, layout.h_leaf_min, G, _d(rho), s.size,
+                                  s.ctypes.data_as(_i64p), _d(phi), _d(g))
+    _check(rc, "amr_fmm_sinks")
+    return phi, g
+
+
+def amr_direct(layout, rho, sinks=None, G=None):
+    """Direct sum over all leaf cells (point masses rho h_l^3 at the centres)."""
+    keep, t = _tree_args(layout)
+    rho = _c64(rho)
+    s = _sinks(layout, sinks)
+    phi = np.zeros(s.size); g = np.zeros((3, s.size))
+    G = layout.G if G is None else G
+    _check(_load().oracle_amr_direct(*t, layout.h_leaf_min, G, _d(rho), s.size, s.ctypes.data_as(_i64p),
+                                     _d(phi), _d(g)), "amr_direct")
+    return phi, g
+
+
+def amr_cover(layout, sink, theta=0.4):
+    """How many times the partners of leaf cell `sink` account for each leaf cell."""
+    keep, t = _tree_args(layout)
+    mult = np.zeros(int(layout.is_leaf.sum()) * 512, dtype=np.int32)
+    _check(_load().oracle_amr_cover(*t, theta, int(sink), mult.ctypes.data_as(_i32p)), "amr_cover")
+    return mult

@@ -858,3 +858,385 @@ int oracle_pair_counts(int L, double theta, int64_t *p2p_out, int64_t *m2l_out)
 {
     return oracle_pair_counts_slab(L, theta, 0, nlev(L < 0 ? 0 : L), p2p_out, m2l_out);
 }
+
+/* ======================================================================== */
+/* Adaptive octrees: leaf sub-grids on several levels                        */
+/* ======================================================================== */
+/*
+ * Nodes are 8^3-cell sub-grids given as (level, coordinates, leaf flag), node
+ * 0 the root and every internal node with its 8 children (Sec. 4.3: the octree
+ * is refined where the solution needs it).  The finest level Lmax has cell
+ * width h, level l has h_l = h 2^(Lmax - l), and a leaf cell is a point mass
+ * m = rho h_l^3 at its centre.  Leaf cell k of leaf node j (j-th leaf in
+ * layout order) has index 512 j + k, x fastest inside the sub-grid.
+ *
+ * The paper names the adaptive tree but not the treatment where refinement
+ * changes.  Reading used here:
+ *   - leaf sub-grids that touch (across a face, an edge or a corner) lie at
+ *     most one level apart (2:1 balance);
+ *   - at each level l the same-level rule of the uniform tree holds between
+ *     all cells that exist at l, leaves and refined cells alike: (A, B) is an
+ *     M2L pair when B is far from A and their parents are near (at the root:
+ *     when B is far);
+ *   - a near pair at level l of two leaves is a P2P pair; a near pair of a
+ *     leaf and a refined cell is a P2P pair between the leaf and each child of
+ *     the refined cell (those children are leaves under 2:1 balance); a near
+ *     pair of two refined cells passes to their children.
+ * Every ordered pair of distinct leaf cells is then accounted for once: the
+ * first level at which their ancestors are far gives the M2L pair, and
+ * ancestors that stay near down to the coarser leaf give a P2P pair.
+ */
+typedef struct {
+    int Lmax;
+    double h, G, r2;
+    int reach;
+    int64_t nn;
+    const int32_t *lvl, *crd;
+    const uint8_t *leaf;
+    int32_t *nid[8];       /* per level: node at sub-grid coordinates, or -1 */
+    int64_t *first;        /* per node: index of its first leaf cell, -1 if internal */
+    int64_t *leaf_node;    /* per leaf sub-grid in layout order: its node */
+    int64_t ncell;
+    double *M;             /* [nn * 512][nc]: moments of every cell of every node */
+    mset s;
+} amr;
+
+static double amr_h(const amr *A, int l) { return A->h * (double)(1 << (A->Lmax - l)); }
+
+static void amr_free(amr *A)
+{
+    for (int l = 0; l < 8; ++l) { free(A->nid[l]); A->nid[l] = NULL; }
+    free(A->first); free(A->leaf_node); free(A->M);
+    A->first = NULL; A->leaf_node = NULL; A->M = NULL;
+    mset_free(&A->s);
+}
+
+static int amr_init(amr *A, int64_t nn, const int32_t *lvl, const int32_t *crd, const uint8_t *leaf,
+                    int p, double theta, double h, double G)
+{
+    memset(A, 0, sizeof(*A));
+    if (nn < 1 || !(theta > 0.0) || !(h > 0.0) || mset_init(&A->s, p)) return -1;
+    A->nn = nn; A->lvl = lvl; A->crd = crd; A->leaf = leaf;
+    A->h = h; A->G = G;
+    const double rn = 1.0 / theta;
+    A->r2 = rn * rn;
+    A->reach = (int)floor(rn);
+    int Lmax = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        if (lvl[i] < 0 || lvl[i] > 7) return -1;
+        if (lvl[i] > Lmax) Lmax = lvl[i];
+    }
+    A->Lmax = Lmax;
+    for (int l = 0; l <= Lmax; ++l) {
+        const int64_t m = (int64_t)1 << l;
+        A->nid[l] = malloc(sizeof(int32_t) * (size_t)(m * m * m));
+        if (!A->nid[l]) return -1;
+        for (int64_t k = 0; k < m * m * m; ++k) A->nid[l][k] = -1;
+    }
+    A->first = malloc(sizeof(int64_t) * (size_t)nn);
+    A->leaf_node = malloc(sizeof(int64_t) * (size_t)nn);
+    if (!A->first || !A->leaf_node) return -1;
+    int64_t nleaf = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        const int l = lvl[i];
+        const int64_t m = (int64_t)1 << l;
+        const int x = crd[3 * i], y = crd[3 * i + 1], z = crd[3 * i + 2];
+        if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) return -1;
+        A->nid[l][(z * m + y) * m + x] = (int32_t)i;
+        if (leaf[i]) A->leaf_node[nleaf] = i;
+        A->first[i] = leaf[i] ? 512 * nleaf++ : -1;
+    }
+    A->ncell = 512 * nleaf;
+    A->M = calloc((size_t)nn * 512 * (size_t)A->s.n, sizeof(double));
+    return A->M ? 0 : -1;
+}
+
+/* node holding cell (x, y, z) of level l, or -1 where the level has no cell */
+static int64_t amr_node(const amr *A, int l, int x, int y, int z)
+{
+    if (l < 0 || l > A->Lmax) return -1;
+    const int n = 8 << l;
+    if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return -1;
+    const int64_t m = (int64_t)1 << l;
+    return A->nid[l][((int64_t)(z >> 3) * m + (y >> 3)) * m + (x >> 3)];
+}
+
+static int64_t amr_slot(int x, int y, int z) { return ((int64_t)(z & 7) * 8 + (y & 7)) * 8 + (x & 7); }
+
+/* 0: no such cell, 1: leaf cell, 2: refined cell */
+static int amr_type(const amr *A, int l, int x, int y, int z)
+{
+    const int64_t nd = amr_node(A, l, x, y, z);
+    if (nd < 0) return 0;
+    return A->leaf[nd] ? 1 : 2;
+}
+
+static const double *amr_moments(const amr *A, int l, int x, int y, int z)
+{
+    return &A->M[((size_t)amr_node(A, l, x, y, z) * 512 + (size_t)amr_slot(x, y, z)) * (size_t)A->s.n];
+}
+
+static double amr_mass(const amr *A, const double *rho, int l, int x, int y, int z)
+{
+    const double hl = amr_h(A, l);
+    return rho[A->first[amr_node(A, l, x, y, z)] + amr_slot(x, y, z)] * hl * hl * hl;
+}
+
+static void amr_centre(const amr *A, int l, int x, int y, int z, double out[3])
+{
+    const double hl = amr_h(A, l);
+    out[0] = (x + 0.5) * hl; out[1] = (y + 0.5) * hl; out[2] = (z + 0.5) * hl;
+}
+
+/* P2M at every leaf cell, M2M into every refined cell, finest level first */
+static void amr_upward(amr *A, const double *rho)
+{
+    const int nc = A->s.n;
+    for (int l = A->Lmax; l >= 0; --l) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t i = 0; i < A->nn; ++i) {
+            if (A->lvl[i] != l) continue;
+            const int bx = 8 * A->crd[3 * i], by = 8 * A->crd[3 * i + 1], bz = 8 * A->crd[3 * i + 2];
+            const double hl = amr_h(A, l), h3 = hl * hl * hl;
+            for (int k = 0; k < 512; ++k) {
+                const int x = bx + (k & 7), y = by + ((k >> 3) & 7), z = bz + (k >> 6);
+                double *Mc = &A->M[((size_t)i * 512 + (size_t)k) * (size_t)nc];
+                if (A->leaf[i]) {
+                    Mc[0] = rho[A->first[i] + k] * h3;
+                    continue;
+                }
+                double zc[3], zk[3], d[3];
+                amr_centre(A, l, x, y, z, zc);
+                for (int b = 0; b < 8; ++b) {
+                    const int cx = 2 * x + (b & 1), cy = 2 * y + ((b >> 1) & 1), cz = 2 * z + (b >> 2);
+                    amr_centre(A, l + 1, cx, cy, cz, zk);
+                    for (int t = 0; t < 3; ++t) d[t] = zk[t] - zc[t];
+                    m2m(&A->s, d, amr_moments(A, l + 1, cx, cy, cz), A->s.p, Mc);
+                }
+            }
+        }
+    }
+}
+
+static int amr_near(const amr *A, int dx, int dy, int dz) { return (double)(dx * dx + dy * dy + dz * dz) <= A->r2; }
+
+static int amr_m2l_rule(const amr *A, int l, const int a[3], const int b[3])
+{
+    if (a[0] == b[0] && a[1] == b[1] && a[2] == b[2]) return 0;
+    if (amr_near(A, b[0] - a[0], b[1] - a[1], b[2] - a[2])) return 0;
+    if (l == 0) return 1;
+    return amr_near(A, (b[0] >> 1) - (a[0] >> 1), (b[1] >> 1) - (a[1] >> 1), (b[2] >> 1) - (a[2] >> 1));
+}
+
+/* Every partner of one leaf cell (level li, cell c): fn(kind, l, B, arg) is
+ * called once per M2L partner (kind 0: cell B of level l) and once per P2P
+ * partner (kind 1: leaf cell B of level l).  Returns -2 when a near refined
+ * cell has a child that is not a leaf (the tree is not 2:1 balanced). */
+typedef void (*amr_visit)(int kind, int l, const int B[3], void *arg);
+
+static int amr_partners(const amr *A, int li, const int c[3], amr_visit fn, void *arg)
+{
+    for (int l = 0; l <= li; ++l) {
+        const int sh = li - l, n = 8 << l;
+        const int a[3] = {c[0] >> sh, c[1] >> sh, c[2] >> sh};
+        int lo[3], hi[3];
+        for (int t = 0; t < 3; ++t) {
+            if (l == 0) { lo[t] = 0; hi[t] = n - 1; continue; }
+            const int q = a[t] >> 1;
+            lo[t] = 2 * (q - A->reach); hi[t] = 2 * (q + A->reach) + 1;
+            if (lo[t] < 0) lo[t] = 0;
+            if (hi[t] > n - 1) hi[t] = n - 1;
+        }
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    const int B[3] = {x, y, z};
+                    if (amr_type(A, l, x, y, z) && amr_m2l_rule(A, l, a, B)) fn(0, l, B, arg);
+                }
+    }
+    /* near cells of the sink's own level, and of its parent's level */
+    for (int up = 0; up <= 1 && up <= li; ++up) {
+        const int l = li - up;
+        const int a[3] = {c[0] >> up, c[1] >> up, c[2] >> up};
+        for (int z = a[2] - A->reach; z <= a[2] + A->reach; ++z)
+            for (int y = a[1] - A->reach; y <= a[1] + A->reach; ++y)
+                for (int x = a[0] - A->reach; x <= a[0] + A->reach; ++x) {
+                    if (x == a[0] && y == a[1] && z == a[2]) continue;
+                    if (!amr_near(A, x - a[0], y - a[1], z - a[2])) continue;
+                    const int t = amr_type(A, l, x, y, z);
+                    const int B[3] = {x, y, z};
+                    if (t == 1) {
+                        fn(1, l, B, arg);              /* same-level leaf, or a coarser leaf near the parent */
+                    } else if (t == 2 && up == 0) {    /* refined near cell: its children */
+                        for (int b = 0; b < 8; ++b) {
+                            const int Bc[3] = {2 * x + (b & 1), 2 * y + ((b >> 1) & 1), 2 * z + (b >> 2)};
+                            if (amr_type(A, l + 1, Bc[0], Bc[1], Bc[2]) != 1) return -2;
+                            fn(1, l + 1, Bc, arg);
+                        }
+                    }
+                }
+    }
+    return 0;
+}
+
+typedef struct {
+    const amr *A;
+    const double *rho;
+    int li, c[3];
+    double xi[3];
+    double *Ci, *CA, *D, *Rs;
+    double phi, g[3];
+} amr_eval;
+
+static void amr_eval_visit(int kind, int l, const int B[3], void *arg)
+{
+    amr_eval *E = arg;
+    const amr *A = E->A;
+    double zB[3];
+    amr_centre(A, l, B[0], B[1], B[2], zB);
+    if (kind == 1) {
+        p2p(A->G, E->xi, zB, amr_mass(A, E->rho, l, B[0], B[1], B[2]), &E->phi, E->g);
+        return;
+    }
+    /* M2L from B into the sink's ancestor of level l, re-expanded exactly to the sink centre */
+    const int sh = E->li - l;
+    const int c[3] = {E->c[0] >> sh, E->c[1] >> sh, E->c[2] >> sh};
+    double zA[3], R[3], d[3];
+    amr_centre(A, l, c[0], c[1], c[2], zA);
+    for (int t = 0; t < 3; ++t) { R[t] = zA[t] - zB[t]; d[t] = E->xi[t] - zA[t]; }
+    memset(E->CA, 0, sizeof(double) * (size_t)A->s.n);
+    m2l(&A->s, A->G, R, amr_moments(A, l, B[0], B[1], B[2]), A->s.p, E->CA, E->D, E->Rs);
+    l2l(&A->s, d, E->CA, E->Ci);
+}
+
+/* leaf cell index -> (level, cell coordinates) */
+static int amr_locate(const amr *A, int64_t cell, int *li, int c[3])
+{
+    if (cell < 0 || cell >= A->ncell) return -1;
+    const int64_t i = A->leaf_node[cell / 512], k = cell % 512;
+    *li = A->lvl[i];
+    c[0] = 8 * A->crd[3 * i] + (int)(k & 7);
+    c[1] = 8 * A->crd[3 * i + 1] + (int)((k >> 3) & 7);
+    c[2] = 8 * A->crd[3 * i + 2] + (int)(k >> 6);
+    return 0;
+}
+
+/* FMM forward on an adaptive octree, evaluated per sink (leaf cell indices):
+ * phi[s] and g[k * nsink + s]. */
+int oracle_amr_sinks(int64_t nn, const int32_t *lvl, const int32_t *crd, const uint8_t *leaf, int p,
+                     double theta, double h, double G, const double *rho, int64_t nsink, const int64_t *sinks,
+                     double *phi, double *g)
+{
+    amr A;
+    if (amr_init(&A, nn, lvl, crd, leaf, p, theta, h, G)) { amr_free(&A); return -1; }
+    amr_upward(&A, rho);
+    const int nc = A.s.n, ex = e_k(&A.s, 0), ey = e_k(&A.s, 1), ez = e_k(&A.s, 2);
+    int rc = 0;
+#pragma omp parallel
+    {
+        amr_eval E;
+        E.A = &A; E.rho = rho;
+        E.Ci = malloc(sizeof(double) * nc); E.CA = malloc(sizeof(double) * nc);
+        E.D = malloc(sizeof(double) * nc); E.Rs = malloc(sizeof(double) * scratch_len(&A.s));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t s = 0; s < nsink; ++s) {
+            int *c = E.c;
+            if (amr_locate(&A, sinks[s], &E.li, c)) {
+#pragma omp atomic write
+                rc = -1;
+                continue;
+            }
+            amr_centre(&A, E.li, c[0], c[1], c[2], E.xi);
+            memset(E.Ci, 0, sizeof(double) * nc);
+            E.phi = 0.0; E.g[0] = E.g[1] = E.g[2] = 0.0;
+            if (amr_partners(&A, E.li, c, amr_eval_visit, &E)) {
+#pragma omp atomic write
+                rc = -2;
+                continue;
+            }
+            phi[s] = E.Ci[0] + E.phi;
+            g[s] = E.g[0] - (p >= 1 ? E.Ci[ex] : 0.0);
+            g[nsink + s] = E.g[1] - (p >= 1 ? E.Ci[ey] : 0.0);
+            g[2 * nsink + s] = E.g[2] - (p >= 1 ? E.Ci[ez] : 0.0);
+        }
+        free(E.Ci); free(E.CA); free(E.D); free(E.Rs);
+    }
+    amr_free(&A);
+    return rc;
+}
+
+/* Direct Newtonian sum over all leaf cells of an adaptive octree (point
+ * masses rho h_l^3 at the cell centres, i != j), at the given sinks. */
+int oracle_amr_direct(int64_t nn, const int32_t *lvl, const int32_t *crd, const uint8_t *leaf, double h,
+                      double G, const double *rho, int64_t nsink, const int64_t *sinks, double *phi, double *g)
+{
+    amr A;
+    if (amr_init(&A, nn, lvl, crd, leaf, 0, 1.0, h, G)) { amr_free(&A); return -1; }
+    double *pos = malloc(sizeof(double) * 3 * (size_t)A.ncell), *mass = malloc(sizeof(double) * (size_t)A.ncell);
+    if (!pos || !mass) { free(pos); free(mass); amr_free(&A); return -1; }
+    for (int64_t i = 0; i < nn; ++i) {
+        if (!leaf[i]) continue;
+        const int l = lvl[i];
+        const double hl = amr_h(&A, l);
+        for (int k = 0; k < 512; ++k) {
+            const int64_t j = A.first[i] + k;
+            amr_centre(&A, l, 8 * crd[3 * i] + (k & 7), 8 * crd[3 * i + 1] + ((k >> 3) & 7), 8 * crd[3 * i + 2] + (k >> 6),
+                       &pos[3 * j]);
+            mass[j] = rho[j] * hl * hl * hl;
+        }
+    }
+    int rc = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < nsink; ++s) {
+        const int64_t i = sinks[s];
+        if (i < 0 || i >= A.ncell) {
+#pragma omp atomic write
+            rc = -1;
+            continue;
+        }
+        double ph = 0.0, gg[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < A.ncell; ++j)
+            if (j != i) p2p(G, &pos[3 * i], &pos[3 * j], mass[j], &ph, gg);
+        phi[s] = ph;
+        g[s] = gg[0]; g[nsink + s] = gg[1]; g[2 * nsink + s] = gg[2];
+    }
+    free(pos); free(mass);
+    amr_free(&A);
+    return rc;
+}
+
+/* Pair cover of one sink: mult[j] = how many times the sink's partners
+ * account for leaf cell j (an M2L partner accounts for every leaf cell under
+ * it).  Exact cover: 1 for every j other than the sink, 0 for the sink. */
+typedef struct { const amr *A; int32_t *mult; } amr_cov;
+
+static void amr_mark(const amr *A, int l, int x, int y, int z, int32_t *mult)
+{
+    const int64_t nd = amr_node(A, l, x, y, z);
+    if (nd < 0) return;
+    if (A->leaf[nd]) { mult[A->first[nd] + amr_slot(x, y, z)] += 1; return; }
+    for (int b = 0; b < 8; ++b) amr_mark(A, l + 1, 2 * x + (b & 1), 2 * y + ((b >> 1) & 1), 2 * z + (b >> 2), mult);
+}
+
+static void amr_cover_visit(int kind, int l, const int B[3], void *arg)
+{
+    amr_cov *V = arg;
+    (void)kind;
+    amr_mark(V->A, l, B[0], B[1], B[2], V->mult);
+}
+
+int oracle_amr_cover(int64_t nn, const int32_t *lvl, const int32_t *crd, const uint8_t *leaf, double theta,
+                     int64_t sink, int32_t *mult)
+{
+    amr A;
+    if (amr_init(&A, nn, lvl, crd, leaf, 0, theta, 1.0, 1.0)) { amr_free(&A); return -1; }
+    int li, c[3];
+    int rc = amr_locate(&A, sink, &li, c);
+    if (!rc) {
+        memset(mult, 0, sizeof(int32_t) * (size_t)A.ncell);
+        amr_cov V = {&A, mult};
+        rc = amr_partners(&A, li, c, amr_cover_visit, &V);
+    }
+    amr_free(&A);
+    return rc;
+}

@@ -280,3 +280,153 @@ def random_density(n: int, seed: int, kind: str = "uniform") -> np.ndarray:
         a[rng.choice(n ** 3, size=k, replace=False)] = rng.uniform(0.5, 2.0, size=k)
         return a.reshape(n, n, n)
     raise ValueError(kind)
+
+
+# --------------------------------------------------------------------------
+# adaptive octrees
+# --------------------------------------------------------------------------
+_NEIGHBOURS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+               if (dx, dy, dz) != (0, 0, 0)]
+
+
+def adaptive_layout(Lmax: int, refine, base: int = 0, h: float = 1.0, G: float = 1.0) -> Layout:
+    """Octree refined top-down: every node above level `base` is refined, and a
+    node of level l in [base, Lmax) is refined where refine(l, coords) says so
+    (coords: int array [k, 3] of sub-grid coordinates; returns bool [k]).  The
+    tree is then balanced 2:1: wherever a node of level l is refined, the 26
+    nodes around it at level l exist (refining their parents as needed), so
+    leaf sub-grids that touch lie at most one level apart.  Nodes are listed
+    level by level, z-major inside a level; h is the finest level's cell width."""
+    if Lmax < 0 or not 0 <= base <= Lmax:
+        raise ValueError("need 0 <= base <= Lmax")
+    refined = [set() for _ in range(Lmax)]
+    nodes = {(0, 0, 0)}
+    for l in range(Lmax):
+        cur = sorted(nodes)
+        arr = np.array(cur, dtype=np.int64).reshape(-1, 3)
+        want = np.ones(len(cur), dtype=bool) if l < base else np.asarray(refine(l, arr), dtype=bool)
+        refined[l] = {c for c, w in zip(cur, want) if w}
+        nodes = {(2 * x + (b & 1), 2 * y + ((b >> 1) & 1), 2 * z + (b >> 2))
+                 for (x, y, z) in refined[l] for b in range(8)}
+    changed = True
+    while changed:
+        changed = False
+        for l in range(Lmax - 1, 0, -1):
+            m = 1 << l
+            for (x, y, z) in list(refined[l]):
+                for dx, dy, dz in _NEIGHBOURS:
+                    q = (x + dx, y + dy, z + dz)
+                    if min(q) < 0 or max(q) >= m:
+                        continue
+                    par = (q[0] >> 1, q[1] >> 1, q[2] >> 1)
+                    if par not in refined[l - 1]:
+                        refined[l - 1].add(par)
+                        changed = True
+    levels, coords, leaf = [], [], []
+    cur = [(0, 0, 0)]
+    for l in range(Lmax + 1):
+        cur = sorted(cur, key=lambda c: (c[2], c[1], c[0]))
+        for c in cur:
+            levels.append(l)
+            coords.append(c)
+            leaf.append(l == Lmax or c not in refined[l])
+        if l < Lmax:
+            cur = [(2 * x + (b & 1), 2 * y + ((b >> 1) & 1), 2 * z + (b >> 2))
+                   for (x, y, z) in cur if (x, y, z) in refined[l] for b in range(8)]
+    level = np.array(levels, dtype=np.int32)
+    coord = np.array(coords, dtype=np.int32).reshape(-1, 3)
+    pos = {(int(l), int(c[0]), int(c[1]), int(c[2])): i for i, (l, c) in enumerate(zip(level, coord))}
+    parent = np.full(level.shape[0], -1, dtype=np.int32)
+    for i, (l, c) in enumerate(zip(level, coord)):
+        if l > 0:
+            parent[i] = pos[(int(l) - 1, int(c[0]) >> 1, int(c[1]) >> 1, int(c[2]) >> 1)]
+    return Layout(level=level, coord=coord, parent=parent, is_leaf=np.array(leaf, dtype=np.uint8),
+                  h_leaf_min=h, G=G)
+
+
+def leaf_cell_centres(layout: Layout) -> tuple:
+    """(centres [n_leaf_cells, 3], cell widths [n_leaf_cells]) in layout order,
+    for a tree whose finest level has cell width layout.h_leaf_min."""
+    Lmax = layout.depth
+    leaves = layout.leaf_nodes
+    l = np.arange(SUBGRID, dtype=np.int64)
+    lz, ly, lx = np.meshgrid(l, l, l, indexing="ij")
+    loc = np.stack([lx.ravel(), ly.ravel(), lz.ravel()], axis=1)                 # [512, 3]
+    hl = layout.h_leaf_min * (2.0 ** (Lmax - layout.level[leaves].astype(np.float64)))
+    cells = layout.coord[leaves].astype(np.int64)[:, None, :] * SUBGRID + loc[None]
+    centres = (cells + 0.5) * hl[:, None, None]
+    return centres.reshape(-1, 3), np.repeat(hl, SUBGRID ** 3)
+
+
+def _polytrope_at(points: np.ndarray, centre, radius: float, rho_c: float, n_index: float = 1.5):
+    if n_index not in _LE_CACHE:
+        _LE_CACHE[n_index] = lane_emden(n_index)
+    xs, ts, xi1 = _LE_CACHE[n_index]
+    r = np.sqrt(((points - np.asarray(centre, dtype=np.float64)) ** 2).sum(axis=-1))
+    inside = r <= radius
+    theta = np.interp(np.where(inside, xi1 * r / radius, 0.0), xs, ts)
+    return np.where(inside, rho_c * np.maximum(theta, 0.0) ** n_index, 0.0)
+
+
+def cfg3_amr(seed: int = 3, base: int = 3, extra: int = 3, thresh: float = 1e-3,
+             with_cotangents: bool = True):
+    """Adaptive octree over a box of (8 * 2^(base + extra))^3 finest cells
+    (h = 1): uniform down to level `base`, then refined `extra` more levels
+    wherever a cell centre of the sub-grid has rho > thresh * rho_peak, and
+    balanced 2:1.  rho: the two n = 1.5 polytropes of the 128^3 workload at the
+    same sizes in finest cells (rho_c 1.0, R 20 and rho_c 0.6, R 14, centres 50
+    apart along x about the box centre) plus a 1e-10 floor, evaluated at the
+    leaf cell centres, times (1 + 0.01 U(-1,1)) drawn in layout order;
+    cotangents w, u ~ N(0,1) per leaf cell follow."""
+    Lmax = base + extra
+    nbox = SUBGRID << Lmax
+    c0 = nbox / 2.0
+    stars = [((c0 - 25.0, c0, c0), 20.0, 1.0), ((c0 + 25.0, c0, c0), 14.0, 0.6)]
+    floor = 1e-10
+    peak = 1.0 + floor
+
+    def rho_at(pts):
+        out = np.full(pts.shape[:-1], floor)
+        for ctr, rad, rc in stars:
+            out = out + _polytrope_at(pts, ctr, rad, rc)
+        return out
+
+    l = np.arange(SUBGRID, dtype=np.float64)
+    lz, ly, lx = np.meshgrid(l, l, l, indexing="ij")
+    loc = np.stack([lx.ravel(), ly.ravel(), lz.ravel()], axis=1)
+
+    def refine(level, coords):
+        hl = float(2 ** (Lmax - level))
+        pts = (coords[:, None, :] * SUBGRID + loc[None] + 0.5) * hl
+        return (rho_at(pts) > thresh * peak).any(axis=1)
+
+    layout = adaptive_layout(Lmax, refine, base=base)
+    rng = np.random.default_rng(seed)
+    centres, _ = leaf_cell_centres(layout)
+    rho = rho_at(centres) * (1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=centres.shape[0]))
+    out = dict(layout=layout, rho=rho, Lmax=Lmax)
+    if with_cotangents:
+        out["w"] = rng.standard_normal(centres.shape[0])
+        out["u"] = rng.standard_normal((3, centres.shape[0]))
+    return out
+
+
+def small_amr(kind: str = "corner", seed: int = 7):
+    """Small adaptive trees for parity cases, with rho ~ U(0.5, 1.5) per leaf
+    cell (seeded, layout order).  'corner': depth 2, one level-1 node refined
+    (7 + 8 leaves); 'blob': depth 3 refined around an off-centre point (the
+    balance refines all of level 1; leaves on levels 2 and 3); 'edge': depth 3 refined along a box edge, so
+    the balance reaches the domain boundary."""
+    if kind == "corner":
+        lay = adaptive_layout(2, lambda l, c: (c == 0).all(axis=1), base=1)
+    elif kind == "blob":
+        p = np.array([2.2, 5.1, 3.4])
+        lay = adaptive_layout(3, lambda l, c: np.linalg.norm((c + 0.5) / (1 << l) * 8 - p, axis=1) < 8.0 / (1 << l) * 1.2,
+                              base=1)
+    elif kind == "edge":
+        lay = adaptive_layout(3, lambda l, c: (c[:, 0] == 0) & (c[:, 1] == 0) & (c[:, 2] <= 1), base=1)
+    else:
+        raise ValueError(kind)
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 1.5, size=lay.n_leaf_cells)
+    return dict(layout=lay, rho=rho)
