@@ -19,6 +19,13 @@
  * whose parents are near, and L2L/L2P back to the leaf centres.  Domain
  * boundaries are isolated (no mass outside the tree).
  *
+ * Adaptive trees (leaves on several levels; Sec. 4.3 refines the octree where
+ * the solution needs it): a leaf cell of level l is a point mass rho h_l^3 at
+ * its centre.  Leaves whose sub-grids touch must lie at most one level apart
+ * (2:1 balance).  The same-level rule above then holds at every level between
+ * all existing cells, leaves included; a leaf near a refined cell of its
+ * level meets that cell's children (leaves one level finer) by exact P2P.
+ *
  * The adjoint returns d rho of  sum_i dphi_i phi_i + sum_i dg_i . g_i  through
  * the same discrete operator (its exact transpose).
  *
@@ -53,7 +60,7 @@ extern "C" {
 #define OT_FMM_INVALID_LAYOUT      -2  /* not a proper octree (see plan_create) */
 #define OT_FMM_UNSUPPORTED_ORDER   -3  /* order other than 3 */
 #define OT_FMM_UNSUPPORTED_THETA   -4  /* theta outside (1/3, 1] */
-#define OT_FMM_UNSUPPORTED_LAYOUT  -5  /* valid octree this build cannot run (leaves at several levels, depth > 6) */
+#define OT_FMM_UNSUPPORTED_LAYOUT  -5  /* valid octree this build cannot run (not 2:1 balanced, depth > 6) */
 #define OT_FMM_OUT_OF_MEMORY       -6  /* host or device allocation failed */
 #define OT_FMM_DEVICE_ERROR        -7  /* a HIP call failed */
 #define OT_FMM_NO_DEVICE_STATE     -8  /* plan created with OT_FMM_HOST_ONLY */
@@ -87,9 +94,9 @@ typedef struct ot_fmm_plan_s *ot_fmm_plan;   /* opaque */
 /* Octree of 8^3-cell sub-grids (paper Sec. 4.3).  Node 0 is the root (level 0,
  * coord (0,0,0), parent -1).  A node of level l has integer sub-grid
  * coordinates in [0, 2^l)^3; its parent has level l-1 and coordinates
- * coord >> 1; a node is either a leaf or has all 8 children.  The leaf cell
- * width is h_leaf_min; a cell of level l is 2^(L-l) times wider, L being the
- * deepest level.  origin (the low corner of the root) shifts every position
+ * coord >> 1; a node is either a leaf or has all 8 children.  Leaves may sit
+ * on several levels (2:1 balanced).  The cell width of the deepest level L is
+ * h_leaf_min; a cell of level l is 2^(L-l) times wider.  origin (the low corner of the root) shifts every position
  * alike and does not change phi or g.  The arrays are read during
  * plan_create only. */
 typedef struct {
@@ -110,8 +117,10 @@ typedef struct {
     int64_t n_nodes;
     int64_t n_leaf_nodes;
     int64_t n_leaf_cells;          /* 512 * n_leaf_nodes */
-    int64_t p2p_pairs;             /* ordered leaf pairs evaluated exactly (both cells in the domain) */
-    int64_t m2l_pairs;             /* ordered M2L pairs over the levels below the leaves */
+    int64_t p2p_pairs;             /* ordered leaf pairs evaluated exactly (both cells in the domain;
+                                      adaptive trees: across levels too) */
+    int64_t m2l_pairs;             /* ordered M2L pairs over the levels below the leaves (adaptive
+                                      trees: below the deepest level, leaf cells included) */
     int64_t m2l_pairs_level[16];   /* per level 0..L-1 */
     double  flops_forward;         /* algorithmic FP64 FLOP per forward (8 per P2P pair, 168 per M2L pair, plus M2M/L2L) */
     double  flops_adjoint;         /* same for the adjoint */
@@ -128,7 +137,10 @@ typedef struct {
  * failure *out is NULL.  Layout errors (INVALID_LAYOUT): root not node 0, a
  * parent index out of range or at the wrong level, coordinates outside the
  * level or not within the parent, duplicate nodes, an internal node without
- * all 8 children, a leaf with children. */
+ * all 8 children, a leaf with children.  UNSUPPORTED_LAYOUT: deeper than 6
+ * levels, or an adaptive tree whose refined sub-grids miss a same-level
+ * neighbour (touching leaves more than one level apart).  Adaptive trees
+ * ignore OT_FMM_AUTOTUNE (the size rule picks each level's chunk count). */
 int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order,
                        uint32_t flags, ot_fmm_plan *out);
 

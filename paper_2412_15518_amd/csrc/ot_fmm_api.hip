@@ -163,15 +163,61 @@ int validate_layout(const ot_octree_layout *lay, ot_fmm_plan P)
     }
     if (L > MAX_DEPTH)
         return fail(OT_FMM_UNSUPPORTED_LAYOUT, "octree deeper than 6 levels (more than 512^3 leaf cells)");
-    for (int64_t i = 0; i < n; ++i)
-        if (lay->is_leaf[i] && lay->level[i] != L)
-            return fail(OT_FMM_UNSUPPORTED_LAYOUT,
-                        "leaves on several levels (adaptive refinement) are not supported by this build");
-
-    // a valid octree whose leaves all sit at level L is the full tree of depth L
+    bool amr = false;
+    for (int64_t i = 0; i < n; ++i) amr = amr || (lay->is_leaf[i] && lay->level[i] != L);
     P->L = L;
     P->n_nodes = n;
     P->n_leaf_nodes = nleaf;
+    P->h = lay->h_leaf_min;
+    P->G = lay->G;
+    if (amr) {
+        // Leaves on several levels.  Per level: the sub-grids' kinds and leaf
+        // indices; then 2:1 balance: the 26 sub-grids around every refined
+        // one exist (so leaves that touch lie at most one level apart)
+        P->amr = true;
+        for (int l = 0; l <= L; ++l) {
+            const size_t m = (size_t)1 << l;
+            P->ntype[l].assign(m * m * m, 0);
+            P->lslot[l].assign(m * m * m, -1);
+        }
+        int64_t k = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int l = lay->level[i];
+            const int x = lay->coord[3 * i], y = lay->coord[3 * i + 1], z = lay->coord[3 * i + 2];
+            const size_t m = (size_t)1 << l, at = ((size_t)z * m + y) * m + x;
+            const int32_t packed = x | (y << 10) | (z << 20);
+            P->ntype[l][at] = lay->is_leaf[i] ? 1 : 2;
+            if (lay->is_leaf[i]) {
+                P->lslot[l][at] = (int32_t)k++;
+                P->lnodes[l].push_back(packed);
+            } else {
+                P->rnodes[l].push_back(packed);
+            }
+        }
+        for (int l = 1; l < L; ++l) {
+            const int m = 1 << l;
+            for (int32_t pk : P->rnodes[l]) {
+                const int x = pk & 1023, y = (pk >> 10) & 1023, z = (pk >> 20) & 1023;
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int qx = x + dx, qy = y + dy, qz = z + dz;
+                            if (qx < 0 || qy < 0 || qz < 0 || qx >= m || qy >= m || qz >= m) continue;
+                            if (P->ntype[l][((size_t)qz * m + qy) * m + qx] == 0) {
+                                char buf[200];
+                                snprintf(buf, sizeof buf,
+                                         "octree is not 2:1 balanced: refined sub-grid (%d,%d,%d) of level %d has no "
+                                         "neighbour at (%d,%d,%d)",
+                                         x, y, z, l, qx, qy, qz);
+                                return fail(OT_FMM_UNSUPPORTED_LAYOUT, buf);
+                            }
+                        }
+            }
+        }
+        return OT_FMM_OK;
+    }
+
+    // a valid octree whose leaves all sit at level L is the full tree of depth L
     const int sL = 1 << L;
     P->leaf_slot.assign((size_t)sL * sL * sL, -1);
     int64_t k = 0;
@@ -180,9 +226,101 @@ int validate_layout(const ot_octree_layout *lay, ot_fmm_plan P)
         const int x = lay->coord[3 * i], y = lay->coord[3 * i + 1], z = lay->coord[3 * i + 2];
         P->leaf_slot[((size_t)z * sL + y) * sL + x] = (int32_t)k++;
     }
-    P->h = lay->h_leaf_min;
-    P->G = lay->G;
     return OT_FMM_OK;
+}
+
+// shift magnitudes e_a(x, x, x) of the leaf L2P (x = h/2); the sign of a
+// component follows the child's octant
+void shift_mags(double x, double *e)
+{
+    const double x2 = 0.5 * x * x;
+    const double v[NC] = {1.0, x, x, x, x2, x * x, x * x, x2, x * x, x2,
+                          x2 * x / 3.0, x2 * x, x2 * x, x * x2, x * x * x, x * x2,
+                          x2 * x / 3.0, x2 * x, x * x2, x2 * x / 3.0};
+    for (int k = 0; k < NC; ++k) e[k] = v[k];
+}
+
+// The leaf pass reads, per parent offset P of its list, the 27 kernel rows
+// of the offsets 2P + e (Kst: K0, K1x, K1y, K1z per row).  The adjoint pass
+// streams one source plane at a time: rows of K0, then of -K1x, -K1y, -K1z
+// (the transpose flips the sign of the odd part).  The rows of Ktab (cell
+// width h) are scaled by s0 (K0) and s1 (K1) for another cell width; with
+// near_only, rows of far offsets (|o|^2 > r2i) are zero.
+void leaf_tables(const std::vector<double> &Ktab, const std::vector<char4> &pl, double s0, double s1, int r2i,
+                 bool near_only, std::vector<double> &Kst, std::vector<double> &Ksa)
+{
+    const size_t nP = pl.size();
+    Kst.assign(nP * 27 * 4, 0.0);
+    for (size_t i = 0; i < nP; ++i)
+        for (int e = 0; e < 27; ++e) {
+            const int ox = 2 * pl[i].x + e % 3 - 1, oy = 2 * pl[i].y + (e / 3) % 3 - 1, oz = 2 * pl[i].z + e / 9 - 1;
+            if (near_only && ox * ox + oy * oy + oz * oz > r2i) continue;
+            for (int j = 0; j < 4; ++j)
+                Kst[(i * 27 + e) * 4 + j] = (j == 0 ? s0 : s1) * Ktab[(size_t)off_index(ox, oy, oz) * 4 + j];
+        }
+    Ksa.assign(4 * nP * 27, 0.0);
+    for (int j = 0; j < 4; ++j)
+        for (size_t i = 0; i < nP; ++i)
+            for (int e = 0; e < 27; ++e)
+                Ksa[((size_t)j * nP + i) * 27 + e] = (j == 0 ? 1.0 : -1.0) * Kst[(i * 27 + e) * 4 + j];
+}
+
+// Coarse-fine kernel rows [near offset][child][K0, K1x, K1y, K1z] for source
+// offsets D = (2 o + sgn (c - 1/2)) h per axis, D = source - sink:
+//   up (sgn = -1): sink = child c of parent Q, source = cell Q + o one level up
+//   down (sgn = +1): sink = a cell B, source = child c of cell B + o one level down
+void cf_table(const std::vector<char4> &pl, double h, double G, int sgn, std::vector<double> &K)
+{
+    K.assign(pl.size() * 8 * 4, 0.0);
+    for (size_t i = 0; i < pl.size(); ++i) {
+        if (!pl[i].x && !pl[i].y && !pl[i].z) continue;
+        const int o[3] = {pl[i].x, pl[i].y, pl[i].z};
+        for (int c = 0; c < 8; ++c) {
+            double D[3];
+            for (int k = 0; k < 3; ++k) D[k] = (2.0 * o[k] + sgn * (((c >> k) & 1) - 0.5)) * h;
+            const double r = std::sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+            double *row = &K[(i * 8 + c) * 4];
+            row[0] = -G / r;
+            for (int k = 0; k < 3; ++k) row[1 + k] = G * D[k] / (r * r * r);
+        }
+    }
+}
+
+// Blocks (64 parents, the leaf pass's grouping) of level l's leaf pass that
+// hold a parent of a listed sub-grid's cells
+std::vector<int32_t> blocks_of(int l, const std::vector<int32_t> &nodes)
+{
+    const int np = 4 << l;
+    const int bx = std::min(np, 64), by = std::min(np, 64 / bx), bz = 64 / (bx * by);
+    const int nbx = np / bx, nby = np / by;
+    std::vector<int32_t> out;
+    for (int32_t pk : nodes) {
+        const int x = pk & 1023, y = (pk >> 10) & 1023, z = (pk >> 20) & 1023;
+        for (int qz = 4 * z; qz < 4 * z + 4; ++qz)
+            for (int qy = 4 * y; qy < 4 * y + 4; ++qy)
+                for (int qx = 4 * x; qx < 4 * x + 4; ++qx)
+                    out.push_back(((qz / bz) * nby + qy / by) * nbx + qx / bx);
+    }
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    return out;
+}
+
+// per level holding leaves of an adaptive tree: blocks and kernel tables
+void build_amr_tables(ot_fmm_plan P)
+{
+    const int L = P->L, r2i = P->dp.r2i;
+    for (int l = 1; l <= L; ++l) {
+        P->lblk[l].clear();
+        if (P->lnodes[l].empty()) continue;
+        P->lblk[l] = blocks_of(l, P->lnodes[l]);
+        const double hl = P->h * (double)(1 << (L - l)), r = P->h / hl;
+        leaf_tables(P->Ktab, P->plist_near, r, r * r, r2i, l < L, P->Kst_l[l], P->Ksa_l[l]);
+        P->Kup_l[l].clear();
+        P->Kdn_l[l].clear();
+        if (!P->lnodes[l - 1].empty()) cf_table(P->plist_near, hl, P->G, -1, P->Kup_l[l]);
+        if (l < L && !P->lnodes[l + 1].empty()) cf_table(P->plist_near, 0.5 * hl, P->G, +1, P->Kdn_l[l]);
+    }
 }
 
 void build_tables(ot_fmm_plan P)
@@ -220,24 +358,8 @@ void build_tables(ot_fmm_plan P)
                 K[1] = c * x; K[2] = c * y; K[3] = c * z;
             }
 
-    // the leaf pass reads, per parent offset P of its list, the 27 rows 2P + e
     const std::vector<char4> &pl = (L == 0) ? P->plist_cube : P->plist_near;
-    P->Kst.assign(pl.size() * 27 * 4, 0.0);
-    for (size_t i = 0; i < pl.size(); ++i)
-        for (int e = 0; e < 27; ++e) {
-            const int ox = 2 * pl[i].x + e % 3 - 1, oy = 2 * pl[i].y + (e / 3) % 3 - 1, oz = 2 * pl[i].z + e / 9 - 1;
-            for (int j = 0; j < 4; ++j)
-                P->Kst[(i * 27 + e) * 4 + j] = P->Ktab[(size_t)off_index(ox, oy, oz) * 4 + j];
-        }
-
-    // the adjoint leaf pass streams one source plane at a time: rows of K0,
-    // then of -K1x, -K1y, -K1z (the transpose flips the sign of the odd part)
-    const size_t nP = pl.size();
-    P->Ksa.assign(4 * nP * 27, 0.0);
-    for (int j = 0; j < 4; ++j)
-        for (size_t i = 0; i < nP; ++i)
-            for (int e = 0; e < 27; ++e)
-                P->Ksa[((size_t)j * nP + i) * 27 + e] = (j == 0 ? 1.0 : -1.0) * P->Kst[(i * 27 + e) * 4 + j];
+    leaf_tables(P->Ktab, pl, 1.0, 1.0, r2i, false, P->Kst, P->Ksa);
 
     // tree passes over the levels 0..L-2 in spans of at most three levels,
     // aligned to the bottom: [L-4, L-2], [L-7, L-5], ... and a shorter top span
@@ -258,16 +380,7 @@ void build_tables(ot_fmm_plan P)
         P->dp.n_span = n;
     }
 
-    // shift magnitudes e_a(x, x, x) of the leaf L2P (x = h/2); the sign of a
-    // component follows the child's octant
-    auto mags = [](double x, double *e) {
-        const double x2 = 0.5 * x * x;
-        const double v[NC] = {1.0, x, x, x, x2, x * x, x * x, x2, x * x, x2,
-                              x2 * x / 3.0, x2 * x, x2 * x, x * x2, x * x * x, x * x2,
-                              x2 * x / 3.0, x2 * x, x * x2, x2 * x / 3.0};
-        for (int k = 0; k < NC; ++k) e[k] = v[k];
-    };
-    mags(0.5 * h, P->dp.e_leaf);
+    shift_mags(0.5 * h, P->dp.e_leaf);
 
     // derivative tensors per level l < L at R = z_sink - z_source = -o h_l
     const int nlev = std::max(L, 1);
@@ -320,8 +433,16 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
         const int nP = (int)pl.size();
         U[l] = (int64_t)np * np * np / 64 * nP;
         P->umask[l].assign((size_t)((U[l] + 31) / 32), 0u);
+        // adaptive trees: only blocks that hold cells of existing sub-grids
+        std::vector<char> live;
+        if (P->amr) {
+            std::vector<int32_t> all(P->lnodes[l]);
+            all.insert(all.end(), P->rnodes[l].begin(), P->rnodes[l].end());
+            live.assign((size_t)(U[l] / nP), 0);
+            for (int32_t b : blocks_of(l, all)) live[(size_t)b] = 1;
+        }
         for (int64_t u = 0; u < U[l]; ++u)
-            if (unit_has_sources(np, (int)(u / nP), pl[u % nP])) {
+            if (unit_has_sources(np, (int)(u / nP), pl[u % nP]) && (live.empty() || live[(size_t)(u / nP)])) {
                 P->umask[l][u >> 5] |= 1u << (u & 31);
                 pos[l].push_back(u);
             }
@@ -365,6 +486,81 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
     }
 }
 
+// Adaptive trees: ordered pairs by enumeration over the cells of every
+// existing sub-grid.  M2L pairs per level (existing sink and source); P2P
+// pairs: leaf pairs of one level (near ones, and at the finest level the far
+// stencil too, which its leaf pass sums directly) and the coarse-fine pairs.
+void fill_info_amr(ot_fmm_plan P)
+{
+    ot_fmm_info &I = P->info;
+    const int L = P->L, r2i = P->dp.r2i;
+    auto kind = [&](int l, int x, int y, int z) -> int {
+        const int n = 8 << l;
+        if (l < 0 || l > L || x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return 0;
+        const size_t m = (size_t)1 << l;
+        return P->ntype[l][((size_t)(z >> 3) * m + (y >> 3)) * m + (x >> 3)];
+    };
+    auto near = [&](int dx, int dy, int dz) { return dx * dx + dy * dy + dz * dz <= r2i; };
+    int64_t p2p = 0, m2l = 0;
+    for (int l = 0; l <= L; ++l) {
+        int64_t cnt_m2l = 0, cnt_p2p = 0;
+        std::vector<int32_t> all(P->lnodes[l]);
+        all.insert(all.end(), P->rnodes[l].begin(), P->rnodes[l].end());
+        for (int32_t pk : all) {
+            const int sx = pk & 1023, sy = (pk >> 10) & 1023, sz = (pk >> 20) & 1023;
+            const bool leaf = kind(l, 8 * sx, 8 * sy, 8 * sz) == 1;
+            for (int k = 0; k < 512; ++k) {
+                const int x = 8 * sx + (k & 7), y = 8 * sy + ((k >> 3) & 7), z = 8 * sz + (k >> 6);
+                // same-level stencil: the children of the parents near the
+                // cell's parent (the whole root sub-grid at the root)
+                const int r = (int)std::sqrt((double)r2i);
+                const std::vector<char4> &pl = (l == 0) ? P->plist_cube : P->plist_near;
+                for (size_t ip = 0; ip < pl.size() * 8; ++ip) {
+                            const char4 Pc = pl[ip >> 3];
+                            const int bp = (int)(ip & 7);
+                            const int bx = 2 * ((x >> 1) + Pc.x) + (bp & 1), by = 2 * ((y >> 1) + Pc.y) + ((bp >> 1) & 1),
+                                      bz = 2 * ((z >> 1) + Pc.z) + (bp >> 2);
+                            const int dx = bx - x, dy = by - y, dz = bz - z;
+                            const int t = kind(l, bx, by, bz);
+                            if (!t || (!dx && !dy && !dz)) continue;
+                            if (near(dx, dy, dz)) {
+                                if (leaf && t == 1) ++cnt_p2p;
+                                else if (leaf && t == 2) cnt_p2p += 8;       // the refined cell's children
+                                continue;
+                            }
+                            if (l > 0 && !near((bx >> 1) - (x >> 1), (by >> 1) - (y >> 1), (bz >> 1) - (z >> 1)))
+                                continue;
+                            if (l == L) ++cnt_p2p;      // finest level: the leaf pass sums them directly
+                            else ++cnt_m2l;
+                        }
+                // a leaf's coarse-fine pairs with the leaves near its parent
+                if (leaf && l > 0)
+                    for (int dz = -r; dz <= r; ++dz)
+                        for (int dy = -r; dy <= r; ++dy)
+                            for (int dx = -r; dx <= r; ++dx)
+                                if ((dx || dy || dz) && near(dx, dy, dz) &&
+                                    kind(l - 1, (x >> 1) + dx, (y >> 1) + dy, (z >> 1) + dz) == 1)
+                                    ++cnt_p2p;
+            }
+        }
+        if (l < L) I.m2l_pairs_level[l] = cnt_m2l;
+        m2l += cnt_m2l;
+        p2p += cnt_p2p;
+    }
+    I.p2p_pairs = p2p;
+    I.m2l_pairs = m2l;
+    int64_t refined_cells = 0;
+    for (int l = 1; l < L; ++l) refined_cells += 512 * (int64_t)P->rnodes[l].size();
+    const double N = (double)I.n_leaf_cells;
+    const double tree = 2.0 * 84.0 * 2.0 * (double)refined_cells;
+    I.flops_forward = 8.0 * (double)p2p + 168.0 * (double)m2l + tree + 2.0 * (20.0 + 50.0) * N;
+    I.flops_adjoint = 8.0 * (double)p2p + 168.0 * (double)m2l + tree + 2.0 * (50.0 + 20.0) * N;
+    int64_t cells = 0;
+    for (int l = 0; l < L; ++l) cells += 512 * (int64_t)(P->rnodes[l].size() + P->lnodes[l].size());
+    I.bytes_forward = 8.0 * N + 32.0 * N + 4.0 * NC * 8.0 * (double)cells;
+    I.bytes_adjoint = 32.0 * N + 8.0 * N + 4.0 * NC * 8.0 * (double)cells;
+}
+
 // ordered pairs and algorithmic work of the plan
 void fill_info(ot_fmm_plan P)
 {
@@ -404,6 +600,10 @@ void fill_info(ot_fmm_plan P)
         return tot;
     };
 
+    if (P->amr) {
+        fill_info_amr(P);
+        return;
+    }
     const int64_t N = I.n_leaf_cells;
     I.p2p_pairs = (L == 0) ? (int64_t)512 * 511 : parity_sum(8 << L, false);
     int64_t m2l = 0;
@@ -517,6 +717,73 @@ int autotune_leaf(ot_fmm_plan P)
     return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "leaf autotuning");
 }
 
+// stencil chunks of a leaf pass over nblk blocks: the smallest power of two
+// that gives a launch of at least 16384 waves (see setup_device)
+int chunk_rule(int64_t nblk)
+{
+    int c = 1;
+    while (c < LEAF_MAX_CHUNKS && nblk * c < 16384) c *= 2;
+    return c;
+}
+
+// Adaptive trees: node kinds and lists on the device, and one view of the
+// plan per level that holds leaves (its leaf pass and coarse-fine pass)
+int setup_amr_views(ot_fmm_plan P)
+{
+    DevPlan &d = P->dp;
+    const int L = P->L;
+    int rc;
+    for (int l = 0; l <= L; ++l) {
+        const uint8_t *nt = nullptr;
+        if ((rc = dev_upload(P, &nt, P->ntype[l]))) return rc;
+        P->dev_ntype[l] = nt;
+        if (l < L) d.lev[l].ntype = nt;
+        if ((rc = dev_upload(P, &P->dev_lnodes[l], P->lnodes[l]))) return rc;
+        if ((rc = dev_upload(P, &P->dev_rnodes[l], P->rnodes[l]))) return rc;
+    }
+    double *srcs[MAX_LEVELS] = {};
+    for (int l = 1; l <= L; ++l) {
+        if (P->lnodes[l].empty()) continue;
+        DevPlan &v = P->view[l];
+        v = d;
+        const double hl = P->h * (double)(1 << (L - l));
+        v.L = l;
+        v.hleaf = hl;
+        v.h3 = hl * hl * hl;
+        v.sL = 1 << l;
+        v.npL = 4 << l;
+        v.hpL = 2;
+        v.ppL = v.npL + 2 * v.hpL;
+        if ((rc = dev_upload(P, &v.leaf_slot, P->lslot[l]))) return rc;
+        if ((rc = dev_upload(P, &v.Kst, P->Kst_l[l]))) return rc;
+        if ((rc = dev_upload(P, &v.Ksa, P->Ksa_l[l]))) return rc;
+        v.plist_leaf = d.plist_near;
+        v.n_plist_leaf = d.n_plist_near;
+        shift_mags(0.5 * hl, v.e_leaf);
+        const size_t pp3 = (size_t)v.ppL * v.ppL * v.ppL;
+        if ((rc = dev_alloc(P, &srcs[l], 4 * 8 * pp3, true))) return rc;
+        v.src = srcs[l];
+        v.own_pieces = l < L ? 1 : 0;
+        if ((rc = dev_upload(P, &v.blist, P->lblk[l]))) return rc;
+        v.nblist = (int)P->lblk[l].size();
+        v.Kcf_up = v.Kcf_dn = nullptr;
+        if (!P->Kup_l[l].empty() && (rc = dev_upload(P, &v.Kcf_up, P->Kup_l[l]))) return rc;
+        if (!P->Kdn_l[l].empty() && (rc = dev_upload(P, &v.Kcf_dn, P->Kdn_l[l]))) return rc;
+        v.leaf_chunks[0] = v.leaf_chunks[1] = chunk_rule(v.nblist);
+    }
+    for (int l = 1; l <= L; ++l) {
+        if (P->lnodes[l].empty()) continue;
+        DevPlan &v = P->view[l];
+        v.src_up = v.Kcf_up ? srcs[l - 1] : nullptr;
+        v.hp_up = 2;
+        v.pp_up = (4 << (l - 1)) + 4;
+        v.src_dn = v.Kcf_dn ? srcs[l + 1] : nullptr;
+        v.hp_dn = 2;
+        v.pp_dn = (4 << (l + 1)) + 4;
+    }
+    return OT_FMM_OK;
+}
+
 int setup_device(ot_fmm_plan P)
 {
     hipError_t e = hipGetDevice(&P->device);
@@ -558,7 +825,8 @@ int setup_device(ot_fmm_plan P)
     d.n_plist_leaf = (L == 0) ? d.n_plist_cube : d.n_plist_near;
     d.n_mdesc = (int)P->mdesc.size();
     const size_t ppL3 = (size_t)d.ppL * d.ppL * d.ppL;
-    if ((rc = dev_alloc(P, &d.src, 4 * 8 * ppL3, true))) return rc;
+    d.src = nullptr;
+    if (!P->amr && (rc = dev_alloc(P, &d.src, 4 * 8 * ppL3, true))) return rc;
     for (int l = 0; l < L; ++l) {
         DevLevel &v = d.lev[l];
         v.np = 4 << l;
@@ -576,6 +844,7 @@ int setup_device(ot_fmm_plan P)
         // level L-1 itself, from the leaf sources)
         bool full = false;
         for (int i = 1; i < d.n_span; ++i) full = full || (l == d.span_top[i]);
+        if (P->amr) full = l >= 1 && !P->rnodes[l].empty();     // the M2M of level l - 1 reads them
         v.M = nullptr;
         v.Mr = nullptr;
         v.M32 = nullptr;
@@ -590,23 +859,22 @@ int setup_device(ot_fmm_plan P)
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }
+    if (P->amr && (rc = setup_amr_views(P))) return rc;
     // stencil chunks of the leaf passes: the smallest power of two that gives
     // a launch at least 16384 waves (four rounds of the 4096 wave slots the
     // leaf kernels' registers leave), at most LEAF_MAX_CHUNKS per block.  The
     // timing tuner picks the same counts at depths 1..4 (8, 8, 8, 4) and at
     // depth 5 (1) for the adjoint.
-    const int64_t nblk = (int64_t)d.npL * d.npL * d.npL / 64;
-    int c = 1;
-    while (c < LEAF_MAX_CHUNKS && nblk * c < 16384) c *= 2;
-    d.leaf_chunks[0] = d.leaf_chunks[1] = c;
+    d.leaf_chunks[0] = d.leaf_chunks[1] = chunk_rule((int64_t)d.npL * d.npL * d.npL / 64);
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize after plan setup");
-    if ((P->flags & OT_FMM_AUTOTUNE) && (rc = autotune_leaf(P))) return rc;
+    if ((P->flags & OT_FMM_AUTOTUNE) && !P->amr && (rc = autotune_leaf(P))) return rc;
     P->has_device = true;
     return OT_FMM_OK;
 }
 
 bool misaligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) != 0; }
+
 
 // --------------------------------------------------------------------------
 // timing of kernel phases with events on the call's stream
@@ -670,6 +938,61 @@ hipError_t tree_passes(ot_fmm_plan P, hipStream_t s)
         ph.end();
     }
     return e;
+}
+
+// Adaptive trees, forward (adj 0: rho -> phi, g) or adjoint (adj 1: dphi, dg
+// -> drho): leaf moments and M2M level by level, the M2L of every level, the
+// L2L spans, then per level holding leaves its leaf pass and its coarse-fine
+// pairs.
+int amr_run(ot_fmm_plan P, int adj, const double *a0, const double *a1, double *out0, double *out1, hipStream_t s)
+{
+    const DevPlan &d = P->dp;
+    const int L = P->L;
+    hipError_t e;
+    {
+        int nl = 0;
+        for (int l = 0; l <= L; ++l) nl += (l >= 1 && l < L && !P->lnodes[l].empty()) + !P->rnodes[l].empty();
+        Phase ph(P, s, adj ? OT_FMM_PHASE_UPWARD_LEAF_ADJ : OT_FMM_PHASE_UPWARD_LEAF, nl);
+        for (int l = 1; l < L; ++l)
+            if (!P->lnodes[l].empty() &&
+                (e = launch_amr_leaf_moments(P->view[l], adj, P->dev_lnodes[l], (int)P->lnodes[l].size(), a0, a1,
+                                             s)) != hipSuccess)
+                return hip_fail(e, "launch of the leaf moments");
+        for (int l = L - 1; l >= 0; --l) {
+            const DevPlan &v = P->lnodes[l + 1].empty() ? d : P->view[l + 1];
+            if ((e = launch_amr_m2m(v, adj, l, P->dev_rnodes[l], (int)P->rnodes[l].size(), P->dev_ntype[l + 1], a0,
+                                    a1, s)) != hipSuccess)
+                return hip_fail(e, "launch of an M2M level");
+        }
+        ph.end();
+    }
+    {
+        Phase ph(P, s, OT_FMM_PHASE_M2L, 1);
+        if ((e = launch_m2l(d, s)) != hipSuccess) return hip_fail(e, "launch m2l");
+        ph.end();
+    }
+    if (d.n_span > 0) {
+        Phase ph(P, s, OT_FMM_PHASE_L2L, d.n_span);
+        for (int i = 0; i < d.n_span; ++i)
+            if ((e = launch_l2l_span(d, i, s)) != hipSuccess) return hip_fail(e, "launch l2l");
+        ph.end();
+    }
+    {
+        int nl = 0;
+        for (int l = 1; l <= L; ++l) nl += P->lnodes[l].empty() ? 0 : 1 + (l < L || P->view[l].src_up != nullptr);
+        Phase ph(P, s, adj ? OT_FMM_PHASE_LEAF_ADJ : OT_FMM_PHASE_LEAF, nl);
+        for (int l = 1; l <= L; ++l) {
+            if (P->lnodes[l].empty()) continue;
+            const DevPlan &v = P->view[l];
+            if ((e = launch_leaf_chunks(v, adj, v.leaf_chunks[adj], out0, out1, s)) != hipSuccess)
+                return hip_fail(e, "launch of a leaf pass");
+        }
+        for (int l = 1; l <= L; ++l)
+            if (!P->lnodes[l].empty() && (e = launch_amr_cf(P->view[l], adj, out0, out1, s)) != hipSuccess)
+                return hip_fail(e, "launch of a coarse-fine pass");
+        ph.end();
+    }
+    return OT_FMM_OK;
 }
 
 }  // namespace
@@ -831,6 +1154,7 @@ int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order, 
     if (rc) { delete P; return rc; }
     try {
         build_tables(P);
+        if (P->amr) build_amr_tables(P);
         fill_info(P);
     } catch (const std::bad_alloc &) {
         delete P;
@@ -865,6 +1189,10 @@ int ot_fmm_plan_set_leaf_chunks(ot_fmm_plan P, int forward, int adjoint)
     if (!P->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "plan was created with OT_FMM_HOST_ONLY");
     P->dp.leaf_chunks[0] = forward;
     P->dp.leaf_chunks[1] = adjoint;
+    for (int l = 0; l < MAX_LEVELS; ++l) {      // adaptive trees: every level's leaf pass
+        P->view[l].leaf_chunks[0] = forward;
+        P->view[l].leaf_chunks[1] = adjoint;
+    }
     return OT_FMM_OK;
 }
 
@@ -890,6 +1218,13 @@ int ot_fmm_forward(ot_fmm_plan P, const double *rho, double *phi, double *g, voi
     const DevPlan &d = P->dp;
     hipError_t e;
     Phase total(P, s, OT_FMM_PHASE_TOTAL, 0);
+    if (P->amr) {
+        const int rc = amr_run(P, 0, rho, nullptr, phi, g, s);
+        if (rc) return rc;
+        total.end();
+        if (P->timing.active && P->timing.calls < P->timing.max_calls) P->timing.calls++;
+        return OT_FMM_OK;
+    }
     {
         Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF, 1);
         if ((e = launch_upward_leaf(d, rho, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf");
@@ -918,6 +1253,13 @@ int ot_fmm_adjoint(ot_fmm_plan P, const double *dphi, const double *dg, double *
     const DevPlan &d = P->dp;
     hipError_t e;
     Phase total(P, s, OT_FMM_PHASE_TOTAL, 0);
+    if (P->amr) {
+        const int rc = amr_run(P, 1, dphi, dg, drho, nullptr, s);
+        if (rc) return rc;
+        total.end();
+        if (P->timing.active && P->timing.calls < P->timing.max_calls) P->timing.calls++;
+        return OT_FMM_OK;
+    }
     {
         Phase ph(P, s, OT_FMM_PHASE_UPWARD_LEAF_ADJ, 1);
         if ((e = launch_upward_leaf_adj(d, dphi, dg, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf_adj");

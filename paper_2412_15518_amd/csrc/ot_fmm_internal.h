@@ -62,6 +62,7 @@ struct DevLevel {
     double *C;       // [NC][8][np^3] local coefficients (final); null at level L-1
     double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
     const uint32_t *umask;   // bit u: M2L unit u (block u / nP, offset u % nP) has a source in the domain
+    const uint8_t *ntype;    // adaptive trees: per sub-grid of the level, 0 none, 1 leaf, 2 refined (else null)
 };
 
 // M2L work: a block = 64 sink parents of one level (bx*by*bz parents, lane =
@@ -106,6 +107,16 @@ struct DevPlan {
     int n_span; int span_top[MAX_LEVELS], span_n[MAX_LEVELS];   // tree passes over levels 0..L-2
     double e_leaf[NC];   // e_a(h/2, h/2, h/2): L2P shift magnitudes, leaf cell from its parent
     int leaf_chunks[2];  // stencil chunks (waves per block) of the forward and adjoint leaf passes
+    // Adaptive trees (leaves on several levels).  The plan keeps one copy of
+    // this struct per level that holds leaves (a "view": L is that level and
+    // the leaf fields above describe its leaves); the level arrays lev[] are
+    // shared.  Uniform trees leave all of these null / 0.
+    int own_pieces;              // leaf cells of this level are M2L sinks too (levels below the finest)
+    const int32_t *blist; int nblist;   // blocks of the leaf pass holding a leaf sub-grid of this level
+    const double *src_up, *src_dn;      // source planes of levels L-1 and L+1 (null without leaves there)
+    int hp_up, pp_up, hp_dn, pp_dn;
+    const double *Kcf_up;        // [n_plist_near][8][4]: kernel rows, child c of a parent to a leaf of level L-1
+    const double *Kcf_dn;        // [n_plist_near][8][4]: kernel rows, cell of level L to child c' of a level-L cell
     DevLevel lev[MAX_LEVELS];
 };
 
@@ -137,6 +148,18 @@ struct ot_fmm_plan_s {
     std::vector<int32_t> leaf_slot;
     std::vector<char4> plist_near, plist_cube;
     std::vector<otfmm::M2LDesc> mdesc;
+    // adaptive trees
+    bool amr = false;
+    std::vector<uint8_t> ntype[otfmm::MAX_LEVELS];     // per level and sub-grid: 0 none, 1 leaf, 2 refined
+    std::vector<int32_t> lslot[otfmm::MAX_LEVELS];     // per level and sub-grid: leaf index, or -1
+    std::vector<int32_t> lnodes[otfmm::MAX_LEVELS];    // leaf sub-grids per level, packed x | y << 10 | z << 20
+    std::vector<int32_t> rnodes[otfmm::MAX_LEVELS];    // refined sub-grids per level, packed alike
+    std::vector<int32_t> lblk[otfmm::MAX_LEVELS];      // leaf-pass blocks per level
+    std::vector<double> Kst_l[otfmm::MAX_LEVELS], Ksa_l[otfmm::MAX_LEVELS];
+    std::vector<double> Kup_l[otfmm::MAX_LEVELS], Kdn_l[otfmm::MAX_LEVELS];
+    otfmm::DevPlan view[otfmm::MAX_LEVELS];            // per level holding leaves
+    const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
+    const uint8_t *dev_ntype[otfmm::MAX_LEVELS] = {};
     std::vector<uint32_t> umask[otfmm::MAX_LEVELS];   // M2L units with sources in the domain, per level
     std::vector<double> Ktab, Kst, Ksa, Dtab;
     std::vector<float> Dtab32;
@@ -162,5 +185,16 @@ hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s);
 hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s);
 // either leaf pass with an explicit chunk count (1 .. LEAF_MAX_CHUNKS)
 hipError_t launch_leaf_chunks(const DevPlan &p, int adj, int nchunk, double *out0, double *out1, hipStream_t s);
+// adaptive trees: v is the view of the level named in each comment
+//   moments of the n leaf sub-grids of level v.L (M2L sources)
+hipError_t launch_amr_leaf_moments(const DevPlan &v, int adj, const int32_t *nodes, int n, const double *a0,
+                                   const double *a1, hipStream_t s);
+//   moments of the n refined sub-grids of level l (v: view of level l + 1, or
+//   any plan whose lev[] is the tree's when level l + 1 holds no leaves)
+hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes, int n, const uint8_t *child_type,
+                          const double *a0, const double *a1, hipStream_t s);
+//   for the leaves of level v.L: their own level's M2L part (below the finest
+//   level) and their P2P pairs with leaves one level up or down
+hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, hipStream_t s);
 
 }  // namespace otfmm

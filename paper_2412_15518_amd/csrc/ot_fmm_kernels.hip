@@ -940,10 +940,14 @@ __global__ __launch_bounds__(L2L_SPAN_WG) void k_l2l_span(const DevPlan p, int l
     const int t = threadIdx.x;
     const int j = (t == 0) ? 0 : (t < 9 ? 1 : 2);
     const int ci = (t == 0) ? 0 : (t < 9 ? t - 1 : t - 9);
-    const bool act = t < 73 && j < nlev;
+    bool act = t < 73 && j < nlev;
     const int lv = ltop + j;
     int cx, cy, cz;
     span_cell(ax, ay, az, j, ci, cx, cy, cz);
+    if (act && p.lev[lv].ntype) {        // adaptive tree: only cells of existing sub-grids
+        const int64_t m = (int64_t)1 << lv;
+        act = p.lev[lv].ntype[((int64_t)(cz >> 3) * m + (cy >> 3)) * m + (cx >> 3)] != 0;
+    }
     const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
     double C[NC];
 #pragma unroll
@@ -1108,8 +1112,9 @@ __global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, 
     const int npL = p.npL;
     const Block bs = block_shape(npL);
     const int nbx = npL / bs.bx, nby = npL / bs.by, nbz = npL / bs.bz;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    if (blk >= nbx * nby * nbz) return;             // the whole workgroup: no barrier is skipped
+    const int bi = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = p.blist ? (bi < p.nblist ? p.blist[bi] : -1) : bi;
+    if (blk < 0 || blk >= nbx * nby * nbz) return;  // the whole workgroup: no barrier is skipped
     const int chunk = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
@@ -1284,7 +1289,9 @@ __global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, 
     }
 
     const int sgx = Qx >> 2, sgy = Qy >> 2, sgz = Qz >> 2;
-    const int64_t base = (int64_t)p.leaf_slot[((int64_t)sgz * p.sL + sgy) * p.sL + sgx] * 512;
+    const int32_t slot = p.leaf_slot[((int64_t)sgz * p.sL + sgy) * p.sL + sgx];
+    if (slot < 0) return;          // adaptive tree: this parent's children are not leaves of this level
+    const int64_t base = (int64_t)slot * 512;
     const int lx0 = (2 * Qx) & 7, ly0 = (2 * Qy) & 7, lz0 = (2 * Qz) & 7;
     const int64_t N = p.n_leaf_cells;
 #pragma unroll
@@ -1297,6 +1304,208 @@ __global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, 
             out1[2 * N + idx] = acc[b][3 % NA];
         } else {
             out0[idx] = p.h3 * acc[b][0];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Adaptive trees.  Every level keeps the dense arrays of a uniform tree; the
+// cells of sub-grids that do not exist stay zero.  A leaf cell of a level
+// below the finest one is an M2L source and sink of its level; its near pairs
+// are P2P pairs with the leaves of its level, with the children of near
+// refined cells (leaves one level finer) and with the leaves near its parent
+// (one level coarser).
+// ------------------------------------------------------------------------
+
+// cell (x, y, z) of sub-grid `packed` (x | y << 10 | z << 20), k = local index
+__device__ __forceinline__ void amr_cell(int32_t packed, int k, int &x, int &y, int &z)
+{
+    x = 8 * (packed & 1023) + (k & 7);
+    y = 8 * ((packed >> 10) & 1023) + ((k >> 3) & 7);
+    z = 8 * ((packed >> 20) & 1023) + (k >> 6);
+}
+
+// moments of the leaf cells of level p.L (p: that level's view), stored as
+// M2L sources: the point mass, or the dual source (a monopole w and a
+// dipole u at the cell centre)
+template <bool ADJ>
+__global__ __launch_bounds__(WG) void k_amr_leaf_moments(const DevPlan p, const int32_t *__restrict__ nodes,
+                                                         int n, const double *__restrict__ a0,
+                                                         const double *__restrict__ a1)
+{
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * 512) return;
+    const int32_t nd = nodes[t >> 9];
+    const int k = (int)(t & 511);
+    int x, y, z;
+    amr_cell(nd, k, x, y, z);
+    const int64_t idx = (int64_t)p.leaf_slot[((int64_t)(z >> 3) * p.sL + (y >> 3)) * p.sL + (x >> 3)] * 512 + k;
+    double Mq[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Mq[c] = 0.0;
+    if (!ADJ) {
+        Mq[0] = a0[idx] * p.h3;
+    } else {
+        const int64_t N = p.n_leaf_cells;
+        double e[NC];
+        const double u[3] = {a1[idx], a1[N + idx], a1[2 * N + idx]};
+        taylor(0.0, 0.0, 0.0, e);
+        Mq[0] = a0[idx];
+        dipole_apply(Mq, e, u);
+    }
+    store_moments(p.lev[p.L], x, y, z, Mq, false);
+}
+
+// moments of the refined cells of level l: from the sources of leaf children
+// (P2M, staged for the leaf pass; p is the view of level l + 1) or by M2M
+// from the full moments of refined children
+template <bool ADJ>
+__global__ __launch_bounds__(WG) void k_amr_m2m(const DevPlan p, int l, const int32_t *__restrict__ nodes, int n,
+                                                const uint8_t *__restrict__ child_type, const double *__restrict__ a0,
+                                                const double *__restrict__ a1)
+{
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * 512) return;
+    int x, y, z;
+    amr_cell(nodes[t >> 9], (int)(t & 511), x, y, z);
+    const int64_t mc = (int64_t)2 << l;                   // sub-grids per axis one level down
+    const uint8_t ct = child_type[((int64_t)(z >> 2) * mc + (y >> 2)) * mc + (x >> 2)];
+    double Mq[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Mq[c] = 0.0;
+    if (ct == 1) {
+        leaf_p2m<ADJ>(p, a0, a1, x, y, z, Mq);
+    } else {
+        const DevLevel &Dc = p.lev[l + 1];
+        const int64_t pp = Dc.pp, pp3 = pp * pp * pp;
+        const int64_t pad = ((int64_t)(z + Dc.hp) * pp + (y + Dc.hp)) * pp + (x + Dc.hp);
+        const double hh = 0.5 * Dc.h;
+        for (int b = 0; b < 8; ++b) {
+            double Mc[NC], e[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Mc[c] = Dc.M[(c * 8 + b) * pp3 + pad];
+            taylor((b & 1) ? -hh : hh, ((b >> 1) & 1) ? -hh : hh, (b >> 2) ? -hh : hh, e);   // e(z_cell - z_child)
+            m2m_apply(Mq, e, Mc);
+        }
+    }
+    store_moments(p.lev[l], x, y, z, Mq, p.lev[l].M != nullptr);
+}
+
+// source plane value of cell (x, y, z) of a level whose planes are padded by
+// hp parents (pp per axis): plane j, cell stored under its parent
+__device__ __forceinline__ int64_t src_index(int x, int y, int z, int hp, int pp, int j)
+{
+    const int64_t pp3 = (int64_t)pp * pp * pp;
+    const int b = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+    const int64_t pad = ((int64_t)((z >> 1) + hp) * pp + ((y >> 1) + hp)) * pp + ((x >> 1) + hp);
+    return (int64_t)j * 8 * pp3 + ((b >> 1) * pp3 + pad) * 2 + (b & 1);
+}
+
+// What the leaf pass of an adaptive tree's level p.L leaves out (p: that
+// level's view), added to the outputs it wrote.  Lane = one parent Q of the
+// block, its 8 children the sinks.  Below the finest level: the cell's own
+// M2L expansion at its centre (potential, minus the gradient).  Coarse-fine
+// P2P, up: the leaves of level L-1 near Q; down: the children (leaves of
+// level L+1) of the refined cells near each child.
+template <bool ADJ>
+__global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restrict__ out0, double *__restrict__ out1)
+{
+    const int npL = p.npL;
+    const Block bs = block_shape(npL);
+    const int nbx = npL / bs.bx, nby = npL / bs.by;
+    if ((int)blockIdx.x >= p.nblist) return;
+    const int blk = p.blist[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
+    const int Qy = ((blk / nbx) % nby) * bs.by + (lane / bs.bx) % bs.by;
+    const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
+    const int32_t slot = p.leaf_slot[((int64_t)(Qz >> 2) * p.sL + (Qy >> 2)) * p.sL + (Qx >> 2)];
+    if (slot < 0) return;
+    constexpr int NA = ADJ ? 1 : 4;
+    double acc[8][NA];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) acc[b][a] = 0.0;
+    if (p.own_pieces) {
+        const DevLevel &D = p.lev[p.L];
+        const int64_t nq = D.np, nq3 = nq * nq * nq;
+        const int64_t q = ((int64_t)Qz * nq + Qy) * nq + Qx;
+        for (int piece = 0; piece < D.maxp; ++piece) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const double *cp = D.Cp + ((int64_t)piece * NC * 8 + b) * nq3 + q;
+                acc[b][0] += cp[0];
+                if constexpr (!ADJ) {
+                    acc[b][1 % NA] -= cp[1 * 8 * nq3];
+                    acc[b][2 % NA] -= cp[2 * 8 * nq3];
+                    acc[b][3 % NA] -= cp[3 * 8 * nq3];
+                }
+            }
+        }
+    }
+    const int nP = p.n_plist_near;
+    // one pair: kernel row K (K0, K1) against the planes at src index si
+    auto pair = [&](double(&ac)[NA], const double *K, const double *src, int64_t si, int64_t pl) {
+        if constexpr (!ADJ) {
+            const double m = src[si];
+            ac[0] = fma(K[0], m, ac[0]);
+            ac[1 % NA] = fma(K[1], m, ac[1 % NA]);
+            ac[2 % NA] = fma(K[2], m, ac[2 % NA]);
+            ac[3 % NA] = fma(K[3], m, ac[3 % NA]);
+        } else {
+            // transpose: K0 w - K1 . u
+            ac[0] = fma(K[0], src[si], ac[0]);
+            ac[0] = fma(-K[1], src[si + pl], ac[0]);
+            ac[0] = fma(-K[2], src[si + 2 * pl], ac[0]);
+            ac[0] = fma(-K[3], src[si + 3 * pl], ac[0]);
+        }
+    };
+    if (p.src_up) {
+        const int64_t pl = 8 * (int64_t)p.pp_up * p.pp_up * p.pp_up;
+        for (int i = 0; i < nP; ++i) {
+            const char4 P = p.plist_near[i];
+            if (P.x == 0 && P.y == 0 && P.z == 0) continue;
+            const int64_t si = src_index(Qx + P.x, Qy + P.y, Qz + P.z, p.hp_up, p.pp_up, 0);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) pair(acc[b], p.Kcf_up + ((int64_t)i * 8 + b) * 4, p.src_up, si, pl);
+        }
+    }
+    if (p.src_dn) {
+        const int64_t pl = 8 * (int64_t)p.pp_dn * p.pp_dn * p.pp_dn;
+        const int64_t m = p.sL;                           // sub-grids per axis of this level
+        const uint8_t *nt = p.lev[p.L].ntype;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int Bx = 2 * Qx + (b & 1), By = 2 * Qy + ((b >> 1) & 1), Bz = 2 * Qz + (b >> 2);
+            for (int i = 0; i < nP; ++i) {
+                const char4 P = p.plist_near[i];
+                const int Ax = Bx + P.x, Ay = By + P.y, Az = Bz + P.z;
+                if ((P.x == 0 && P.y == 0 && P.z == 0) || Ax < 0 || Ay < 0 || Az < 0 || (Ax >> 3) >= m ||
+                    (Ay >> 3) >= m || (Az >> 3) >= m)
+                    continue;
+                if (nt[((int64_t)(Az >> 3) * m + (Ay >> 3)) * m + (Ax >> 3)] != 2) continue;
+                for (int c = 0; c < 8; ++c) {
+                    const int64_t si = src_index(2 * Ax + (c & 1), 2 * Ay + ((c >> 1) & 1), 2 * Az + (c >> 2),
+                                                 p.hp_dn, p.pp_dn, 0);
+                    pair(acc[b], p.Kcf_dn + ((int64_t)i * 8 + c) * 4, p.src_dn, si, pl);
+                }
+            }
+        }
+    }
+    const int64_t base = (int64_t)slot * 512;
+    const int lx0 = (2 * Qx) & 7, ly0 = (2 * Qy) & 7, lz0 = (2 * Qz) & 7;
+    const int64_t N = p.n_leaf_cells;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int64_t idx = base + ((lz0 + (b >> 2)) * 8 + (ly0 + ((b >> 1) & 1))) * 8 + (lx0 + (b & 1));
+        if constexpr (!ADJ) {
+            out0[idx] += acc[b][0];
+            out1[idx] += acc[b][1 % NA];
+            out1[N + idx] += acc[b][2 % NA];
+            out1[2 * N + idx] += acc[b][3 % NA];
+        } else {
+            out0[idx] += p.h3 * acc[b][0];
         }
     }
 }
@@ -1386,7 +1595,8 @@ hipError_t launch_leaf_chunks(const DevPlan &p, int adj, int nchunk, double *out
 {
     if (nchunk < 1 || nchunk > LEAF_MAX_CHUNKS) return hipErrorInvalidValue;
     const Block bs = block_shape(p.npL);
-    const int64_t nblk = ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
+    const int64_t nblk = p.blist ? (int64_t)p.nblist : ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
+    if (nblk == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nblk + 7) / 8 * 8);               // whole rounds over the 8 XCDs
     const size_t lds = nchunk > 1 ? (size_t)8 * (adj ? 1 : 4) * 64 * sizeof(double) : 0;
     if (adj)
@@ -1406,6 +1616,44 @@ hipError_t launch_leaf(const DevPlan &p, double *phi, double *g, hipStream_t s)
 hipError_t launch_leaf_adj(const DevPlan &p, double *drho, hipStream_t s)
 {
     return launch_leaf_chunks(p, 1, p.leaf_chunks[1], drho, nullptr, s);
+}
+
+}  // namespace otfmm
+
+namespace otfmm {
+
+hipError_t launch_amr_leaf_moments(const DevPlan &v, int adj, const int32_t *nodes, int n, const double *a0,
+                                   const double *a1, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(grid_for((int64_t)n * 512));
+    if (adj)
+        hipLaunchKernelGGL(k_amr_leaf_moments<true>, grid, dim3(WG), 0, s, v, nodes, n, a0, a1);
+    else
+        hipLaunchKernelGGL(k_amr_leaf_moments<false>, grid, dim3(WG), 0, s, v, nodes, n, a0, a1);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes, int n, const uint8_t *child_type,
+                          const double *a0, const double *a1, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(grid_for((int64_t)n * 512));
+    if (adj)
+        hipLaunchKernelGGL(k_amr_m2m<true>, grid, dim3(WG), 0, s, v, l, nodes, n, child_type, a0, a1);
+    else
+        hipLaunchKernelGGL(k_amr_m2m<false>, grid, dim3(WG), 0, s, v, l, nodes, n, child_type, a0, a1);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, hipStream_t s)
+{
+    if (v.nblist <= 0 || (!v.own_pieces && !v.src_up && !v.src_dn)) return hipSuccess;
+    if (adj)
+        hipLaunchKernelGGL(k_amr_cf<true>, dim3(v.nblist), dim3(64), 0, s, v, out0, out1);
+    else
+        hipLaunchKernelGGL(k_amr_cf<false>, dim3(v.nblist), dim3(64), 0, s, v, out0, out1);
+    return hipGetLastError();
 }
 
 }  // namespace otfmm

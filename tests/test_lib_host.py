@@ -226,8 +226,9 @@ def test_layout_errors():
     _expect(fmm.INVALID_LAYOUT, bad)
 
 
-def test_adaptive_layout_is_reported_unsupported():
-    """Leaves on two levels: a valid octree that this build does not run."""
+def test_adaptive_layout_one_refined_node():
+    """Leaves on two levels, built by hand: level-1 node 1 refined into 8
+    level-2 leaves (balanced: every level-1 node exists)."""
     lay = W.uniform_layout(1)
     # refine node 1 (a level-1 leaf) into 8 level-2 leaves
     lv, co, pa, il = list(lay.level), [tuple(c) for c in lay.coord], list(lay.parent), list(lay.is_leaf)
@@ -237,7 +238,8 @@ def test_adaptive_layout_is_reported_unsupported():
         lv.append(2); co.append(c); pa.append(1); il.append(1)
     bad = W.Layout(level=np.array(lv, np.int32), coord=np.array(co, np.int32), parent=np.array(pa, np.int32),
                    is_leaf=np.array(il, np.uint8))
-    assert "several levels" in _expect(fmm.UNSUPPORTED_LAYOUT, bad)
+    info = fmm.Plan(bad, host_only=True).info()
+    assert info["depth"] == 2 and info["n_leaf_cells"] == (7 + 8) * 512
 
 
 def test_too_deep_layout_is_reported_unsupported():
@@ -264,3 +266,23 @@ def test_plan_is_independent_of_layout_buffers():
     info0 = p.info()
     lay.level[:] = -7
     assert p.info() == info0
+
+
+def test_adaptive_layouts_host_only():
+    """Balanced adaptive trees are accepted; the info counts the leaf cells
+    of every level, and the pair counts cover the M2L levels below the finest."""
+    for kind, depth in (("corner", 2), ("edge", 3), ("blob", 3)):
+        lay = W.small_amr(kind)["layout"]
+        p = fmm.Plan(lay, host_only=True)
+        info = p.info()
+        assert info["depth"] == depth
+        assert info["n_leaf_cells"] == lay.n_leaf_cells
+        assert info["p2p_pairs"] > 0 and info["m2l_pairs"] == sum(info["m2l_pairs_level"][:depth])
+        p.close()
+
+
+def test_unbalanced_adaptive_layout_rejected():
+    from test_oracle_amr_pins import unbalanced_layout
+    with pytest.raises(fmm.OTFMMError) as e:
+        fmm.Plan(unbalanced_layout(), host_only=True)
+    assert e.value.status == -5 and "2:1" in str(e.value)
