@@ -15,7 +15,9 @@ pass), timed by HIP events around its launches inside the timed region, against
 the FP64 vector peak of the MI355X.  `cpu_baseline` times the CPU
 oracle (forward + adjoint) on a z-slab of the same workload.  `m2l_fp32` times
 the FP32 M2L plan on the same workload; `batch` times 16 independent small
-octrees plan by plan, as one batch over 4 streams and as HIP graph replays.
+octrees plan by plan, as one batch over 4 streams and as HIP graph replays;
+`amr` times the adaptive-octree workload (leaves on levels 3..6 of a 512^3
+box) and, in the CPU-baseline leg, checks sampled cells against the oracle.
 """
 import argparse
 import hashlib
@@ -156,6 +158,73 @@ def bench_batch(args) -> dict:
             "outputs_identical": same}
 
 
+def bench_amr(args):
+    """The adaptive workload: a 2:1 balanced octree over a 512^3 box, uniform
+    to level 3 and refined three more levels where rho > 1e-3 of the peak
+    (1296 leaf sub-grids on levels 3..6, the two polytropes of the 128^3
+    workload).  One step = forward + adjoint.  Returns the bench object and
+    the sampled GPU outputs for the oracle check."""
+    import numpy as np
+    import torch
+
+    from paper_2412_15518_amd import fmm, workloads as W
+    d = W.cfg3_amr()
+    lay = d["layout"]
+    c0 = time.perf_counter()
+    plan = fmm.Plan(lay)
+    t_plan = time.perf_counter() - c0
+    info = plan.info()
+    N = info["n_leaf_cells"]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()    # noqa: E731
+    rho, w, u = dev(d["rho"]), dev(d["w"]), dev(d["u"]).reshape(-1)
+    phi = torch.empty(N, dtype=torch.float64, device="cuda")
+    g = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    drho = torch.empty(N, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.forward_into(rho, phi, g)
+        plan.adjoint_into(w, u, drho)
+
+    for _ in range(3):
+        step()
+    kp = max(1, min(args.steps, 10))
+    plan.timing_begin(2 * kp)
+    for _ in range(kp):
+        step()
+    prof = plan.timing_end()
+    phases = {k: v for k, v in prof["phases"].items() if k != "total" and v["launches"] > 0}
+    k = max(5, min(args.steps, 50))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / k
+    pairs = 2 * (info["p2p_pairs"] + info["m2l_pairs"])
+    flops = info["flops_forward"] + info["flops_adjoint"]
+    prof_ms = prof["phases"]["total"]["ms"]
+    per_phase = {name: {"avg_ms": v["ms"] / v["events"], "share": v["ms"] / prof_ms} for name, v in phases.items()}
+    m2l_ms = per_phase["m2l"]["avg_ms"]
+    levels = np.bincount(lay.level[lay.leaf_nodes], minlength=lay.depth + 1).tolist()
+    log(f"adaptive tree: {ms:.3f} ms per forward + adjoint step")
+    out = {"workload": "2:1 balanced adaptive octree over a 512^3 box (h = 1): uniform to level 3 (64^3), refined "
+                       "3 more levels where a cell centre has rho > 1e-3 rho_peak; two n=1.5 polytropes (rho_c "
+                       "1.0/0.6, R 20/14 cells, 50 apart) + 1e-10 floor, +-1% noise; one step = forward + adjoint",
+           "leaf_subgrids_per_level": levels, "n_leaf_cells": N, "n_nodes": lay.n_nodes,
+           "plan_create_s": t_plan, "device_bytes": info["device_bytes"],
+           "steps": k, "ms_per_step": ms, "cell_interactions_per_step": pairs,
+           "cell_interactions_per_s": pairs / (ms * 1e-3),
+           "fp64_flops_per_s": flops / (ms * 1e-3), "frac_fp64_peak": flops / (ms * 1e-3) / PEAK_FP64,
+           "m2l_tflops": 168.0 * info["m2l_pairs"] / (m2l_ms * 1e-3) / 1e12, "phases": per_phase}
+    lvl = np.repeat(lay.level[lay.leaf_nodes], 512)
+    rng = np.random.default_rng(23)
+    sk = np.concatenate([rng.choice(np.nonzero(lvl == l)[0], 64, replace=False) for l in np.unique(lvl)])
+    gs = g.reshape(3, N)
+    state = {"layout": lay, "rho": d["rho"], "sinks": sk, "phi": phi[sk].cpu().numpy(),
+             "g": gs[:, sk].cpu().numpy()}
+    return out, state
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +234,8 @@ def main():
                     help="leaf z-layers of the 128^3 grid in the CPU-oracle sample (0: skip)")
     ap.add_argument("--batch", type=int, default=1,
                     help="also time the batch of 16 independent octrees (0: skip)")
+    ap.add_argument("--amr", type=int, default=1,
+                    help="1: also time the adaptive-octree workload (1296 leaf sub-grids, levels 3..6)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before warmup, copy this many MiB device to device once: a plain copy "
                          "kernel of known traffic that calibrates HBM counter readings")
@@ -322,6 +393,9 @@ def main():
 
     if args.batch:
         out["batch"] = bench_batch(args)
+    amr_state = None
+    if args.amr:
+        out["amr"], amr_state = bench_amr(args)
 
     if args.cpu_slab > 0:
         import oracle as O
@@ -356,6 +430,16 @@ def main():
             "phi": float(np.abs(ph32 - po).max() / np.abs(po).max()),
             "g": float(np.sqrt(((gg32 - go) ** 2).sum(0)).max() / np.sqrt((go ** 2).sum(0)).max()),
             "drho": float(np.abs(dr32 - do).max() / np.abs(do).max()), "tolerance": 1e-5}
+        if amr_state is not None:
+            st = amr_state
+            c3 = time.perf_counter()
+            pa, ga = O.amr_fmm_sinks(st["layout"], st["rho"], st["sinks"])
+            c4 = time.perf_counter()
+            out["amr"]["oracle_err"] = {
+                "phi": float(np.abs(st["phi"] - pa).max() / np.abs(pa).max()),
+                "g": float(np.sqrt(((st["g"] - ga) ** 2).sum(0)).max() / np.sqrt((ga ** 2).sum(0)).max()),
+                "norm": f"normwise max-abs over {st['sinks'].size} sampled leaf cells, 64 per leaf level "
+                        f"(oracle: {c4 - c3:.2f} s on {O.threads()} threads)", "tolerance": 1e-12}
     print(json.dumps(out), flush=True)
 
 

@@ -412,16 +412,18 @@ bool unit_has_sources(int np, int blk, char4 P)
 }
 
 // Cut each level's M2L units into runs, G workgroups in all, in proportion
-// to the level's units with sources in the domain (at least one run per
+// to the level's computed units (a source in the domain and, in an adaptive
+// tree, a block with cells of existing sub-grids; at least one run per
 // level); runs are balanced in those units and skip the others.  Records
-// per level the unit mask and how many partial sums a block can receive.
+// per level the list of computed units and how many partial sums a block can
+// receive.
 void build_m2l_schedule(ot_fmm_plan P, int G)
 {
     P->mdesc.clear();
     const int L = P->L;
     for (int l = 0; l < MAX_LEVELS; ++l) {
         P->dp.lev[l].maxp = 0;
-        P->umask[l].clear();
+        P->ulist[l].clear();
     }
     if (L < 1) return;
     std::vector<std::vector<int64_t>> pos(L);     // each level's computed units, in order
@@ -432,7 +434,6 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
         const std::vector<char4> &pl = (l == 0) ? P->plist_cube : P->plist_near;
         const int nP = (int)pl.size();
         U[l] = (int64_t)np * np * np / 64 * nP;
-        P->umask[l].assign((size_t)((U[l] + 31) / 32), 0u);
         // adaptive trees: only blocks that hold cells of existing sub-grids
         std::vector<char> live;
         if (P->amr) {
@@ -443,7 +444,6 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
         }
         for (int64_t u = 0; u < U[l]; ++u)
             if (unit_has_sources(np, (int)(u / nP), pl[u % nP]) && (live.empty() || live[(size_t)(u / nP)])) {
-                P->umask[l][u >> 5] |= 1u << (u & 31);
                 pos[l].push_back(u);
             }
         V[l] = (int64_t)pos[l].size();
@@ -475,10 +475,14 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
             d.ubeg = (int)b[r];
             d.uend = (int)b[r + 1];
             d.nvalid = (int)((int64_t)(r + 1) * V[l] / g - (int64_t)r * V[l] / g);
+            d.vbeg = (int)((int64_t)r * V[l] / g);
             const int64_t first = (int64_t)(d.ubeg / nP) * nP;
             d.piece0 = (d.ubeg == first) ? 0 : r - run_of(first);
             P->mdesc.push_back(d);
         }
+        P->ulist[l].resize(pos[l].size());         // block << 9 | parent offset (nP <= 343)
+        for (size_t k = 0; k < pos[l].size(); ++k)
+            P->ulist[l][k] = (int32_t)(((pos[l][k] / nP) << 9) | (pos[l][k] % nP));
         int maxp = 0;
         for (int64_t blk = 0; blk < U[l] / nP; ++blk)
             maxp = std::max(maxp, run_of(blk * nP + nP - 1) - run_of(blk * nP) + 1);
@@ -764,6 +768,7 @@ int setup_amr_views(ot_fmm_plan P)
         if ((rc = dev_alloc(P, &srcs[l], 4 * 8 * pp3, true))) return rc;
         v.src = srcs[l];
         v.own_pieces = l < L ? 1 : 0;
+        v.ntype_L = P->dev_ntype[l];
         if ((rc = dev_upload(P, &v.blist, P->lblk[l]))) return rc;
         v.nblist = (int)P->lblk[l].size();
         v.Kcf_up = v.Kcf_dn = nullptr;
@@ -855,7 +860,7 @@ int setup_device(ot_fmm_plan P)
             return rc;
         }
         if (l < L - 1 && (rc = dev_alloc(P, &v.C, (size_t)NC * 8 * np3, true))) return rc;
-        if ((rc = dev_upload(P, &v.umask, P->umask[l]))) return rc;
+        if ((rc = dev_upload(P, &v.ulist, P->ulist[l]))) return rc;
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }

@@ -61,7 +61,8 @@ struct DevLevel {
     float *M32;      // [NR/4][8][pp^3][4] the same in FP32 (FP32 M2L; else null)
     double *C;       // [NC][8][np^3] local coefficients (final); null at level L-1
     double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
-    const uint32_t *umask;   // bit u: M2L unit u (block u / nP, offset u % nP) has a source in the domain
+    const int32_t *ulist;    // the M2L units computed (a source in the domain and, in an adaptive tree,
+                             //   a sink in an existing sub-grid), ascending, as block << 9 | offset
     const uint8_t *ntype;    // adaptive trees: per sub-grid of the level, 0 none, 1 leaf, 2 refined (else null)
 };
 
@@ -82,6 +83,7 @@ struct M2LDesc {
     int ubeg, uend;
     int piece0;      // piece of the run's first (possibly partial) block
     int nvalid;      // units of [ubeg, uend) with a source in the domain (the only ones computed)
+    int vbeg;        // the first of them in the level's unit list
 };
 
 struct DevPlan {
@@ -113,6 +115,7 @@ struct DevPlan {
     // shared.  Uniform trees leave all of these null / 0.
     int own_pieces;              // leaf cells of this level are M2L sinks too (levels below the finest)
     const int32_t *blist; int nblist;   // blocks of the leaf pass holding a leaf sub-grid of this level
+    const uint8_t *ntype_L;             // kinds of this level's sub-grids (0 none, 1 leaf, 2 refined)
     const double *src_up, *src_dn;      // source planes of levels L-1 and L+1 (null without leaves there)
     int hp_up, pp_up, hp_dn, pp_dn;
     const double *Kcf_up;        // [n_plist_near][8][4]: kernel rows, child c of a parent to a leaf of level L-1
@@ -160,7 +163,7 @@ struct ot_fmm_plan_s {
     otfmm::DevPlan view[otfmm::MAX_LEVELS];            // per level holding leaves
     const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
     const uint8_t *dev_ntype[otfmm::MAX_LEVELS] = {};
-    std::vector<uint32_t> umask[otfmm::MAX_LEVELS];   // M2L units with sources in the domain, per level
+    std::vector<int32_t> ulist[otfmm::MAX_LEVELS];    // M2L units computed, per level
     std::vector<double> Ktab, Kst, Ksa, Dtab;
     std::vector<float> Dtab32;
     ot_fmm_info info{};

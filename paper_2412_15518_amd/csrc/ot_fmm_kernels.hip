@@ -561,14 +561,16 @@ constexpr int M2L_TBP = 2;                       // source children per tile
 // it changes.
 constexpr int M2L_WG = 512;                       // 8 waves, one per sink child
 
-typedef const __attribute__((address_space(4))) uint32_t cuint32;
+typedef const __attribute__((address_space(4))) int32_t cint32;
 
-// bit u of a level's unit mask: unit u has a source in the domain.  The mask
-// is never written by a kernel; read through the constant address space, its
-// words arrive by scalar loads.
-__device__ __forceinline__ bool unit_computed(const uint32_t *mask, int u)
+// unit k of a level's list of computed units, stored as block << 9 | parent
+// offset.  The list is never written by a kernel; read through the constant
+// address space, its entries arrive by scalar loads.
+__device__ __forceinline__ void unit_at(const int32_t *list, int k, int &blk, int &i)
 {
-    return (((const cuint32 *)mask)[u >> 5] >> (u & 31)) & 1u;
+    const int u = ((const cint32 *)list)[k];
+    blk = u >> 9;
+    i = u & 511;
 }
 
 template <int PAIR, int... I>
@@ -651,17 +653,9 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
     // fetch cursor: block fb, parent offset fi, tile ft.  Wave w loads rows
     // r = w + 8 j of the next tile (component pair r % 8 of tile child r / 8)
     // straight from global memory into LDS, 16 bytes per lane.
-    // the units of the run that have sources in the domain, in order
-    auto next_unit = [&](int &blk, int &i) {
-        do {
-            if (++i == nP) {
-                i = 0;
-                ++blk;
-            }
-        } while (!unit_computed(D.umask, blk * nP + i));
-    };
-    int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
-    if (!unit_computed(D.umask, d.ubeg)) next_unit(fb, fi);
+    // the run's units are entries vbeg .. vbeg + nvalid - 1 of the level's list
+    int fk = d.vbeg, fb, fi, ft = 0;
+    unit_at(D.ulist, fk, fb, fi);
     int fmq = lane_mq(fb);
     auto fetch = [&](double2 (*t)[NR / 2][64]) {
         const char4 P = plist[fi];
@@ -678,7 +672,7 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
 
     // compute cursor; the run's first raw block takes piece piece0, a block
     // that starts inside the run piece 0
-    int cb = fb, ci = fi, ct = 0;
+    int ck = d.vbeg, cb = fb, ci = fi, ct = 0;
     int piece = (cb == d.ubeg / nP) ? d.piece0 : 0;
 
     double C[NR];
@@ -700,7 +694,7 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
             if (++ft == TPP) {
                 ft = 0;
                 const int ob = fb;
-                next_unit(fb, fi);
+                unit_at(D.ulist, ++fk, fb, fi);
                 if (fb != ob) fmq = lane_mq(fb);
             }
             fetch(nxt);
@@ -721,8 +715,8 @@ void k_m2l(const DevPlan p, const double *__restrict__ Dtab, const char4 *__rest
         }
         if (++ct == TPP && k + 1 < ntiles) {
             ct = 0;
-            int nb = cb, ni = ci;
-            next_unit(nb, ni);
+            int nb, ni;
+            unit_at(D.ulist, ++ck, nb, ni);
             if (nb != cb) {                     // block done in this run: store its piece
                 flush();
                 piece = 0;
@@ -824,16 +818,8 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
 
     // fetch cursor as in k_m2l; wave w loads quad row w of the next tile
     // (tile child w / 4, reduced components 4 (w % 4) .. + 3) into LDS
-    auto next_unit = [&](int &blk, int &i) {       // as in k_m2l
-        do {
-            if (++i == nP) {
-                i = 0;
-                ++blk;
-            }
-        } while (!unit_computed(D.umask, blk * nP + i));
-    };
-    int fb = d.ubeg / nP, fi = d.ubeg - (d.ubeg / nP) * nP, ft = 0;
-    if (!unit_computed(D.umask, d.ubeg)) next_unit(fb, fi);
+    int fk = d.vbeg, fb, fi, ft = 0;               // as in k_m2l
+    unit_at(D.ulist, fk, fb, fi);
     int fmq = lane_mq(fb);
     const int ti = b / (NR / 4), tq = b % (NR / 4);
     auto fetch = [&](float4 (*t)[NR / 4][64]) {
@@ -843,7 +829,7 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
     };
     auto loads_done = [&]() { __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0); };
 
-    int cb = fb, ci = fi, ct = 0;
+    int ck = d.vbeg, cb = fb, ci = fi, ct = 0;
     int piece = (cb == d.ubeg / nP) ? d.piece0 : 0;
 
     double C[NR];           // FP64 accumulators of the block
@@ -876,7 +862,7 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
             if (++ft == TPP) {
                 ft = 0;
                 const int ob = fb;
-                next_unit(fb, fi);
+                unit_at(D.ulist, ++fk, fb, fi);
                 if (fb != ob) fmq = lane_mq(fb);
             }
             fetch(nxt);
@@ -899,8 +885,8 @@ void k_m2l_f32(const DevPlan p, const float *__restrict__ Dtab32, const char4 *_
             ct = 0;
             fold();                             // one parent offset done
             if (k + 1 < ntiles) {
-                int nb = cb, ni = ci;
-                next_unit(nb, ni);
+                int nb, ni;
+                unit_at(D.ulist, ++ck, nb, ni);
                 if (nb != cb) {                 // block done in this run: store its piece
                     flush();
                     piece = 0;
@@ -1445,6 +1431,19 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
         }
     }
     const int nP = p.n_plist_near;
+    // the 27 sub-grids around this lane's (at level L): which are refined
+    // (children that are finer leaves) and which are missing (a coarser leaf
+    // covers them); independent loads, then no load decides a branch below
+    const int64_t m = p.sL;
+    const int sgx = Qx >> 2, sgy = Qy >> 2, sgz = Qz >> 2;
+    uint32_t refined = 0, missing = 0;
+    for (int e = 0; e < 27; ++e) {
+        const int x = sgx + e % 3 - 1, y = sgy + (e / 3) % 3 - 1, z = sgz + e / 9 - 1;
+        if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) continue;
+        const uint8_t t = p.ntype_L[((int64_t)z * m + y) * m + x];
+        refined |= (uint32_t)(t == 2) << e;
+        missing |= (uint32_t)(t == 0) << e;
+    }
     // one pair: kernel row K (K0, K1) against the planes at src index si
     auto pair = [&](double(&ac)[NA], const double *K, const double *src, int64_t si, int64_t pl) {
         if constexpr (!ADJ) {
@@ -1461,7 +1460,7 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
             ac[0] = fma(-K[3], src[si + 3 * pl], ac[0]);
         }
     };
-    if (p.src_up) {
+    if (p.src_up && missing) {
         const int64_t pl = 8 * (int64_t)p.pp_up * p.pp_up * p.pp_up;
         for (int i = 0; i < nP; ++i) {
             const char4 P = p.plist_near[i];
@@ -1471,20 +1470,18 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
             for (int b = 0; b < 8; ++b) pair(acc[b], p.Kcf_up + ((int64_t)i * 8 + b) * 4, p.src_up, si, pl);
         }
     }
-    if (p.src_dn) {
+    if (p.src_dn && refined) {
         const int64_t pl = 8 * (int64_t)p.pp_dn * p.pp_dn * p.pp_dn;
-        const int64_t m = p.sL;                           // sub-grids per axis of this level
-        const uint8_t *nt = p.lev[p.L].ntype;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const int Bx = 2 * Qx + (b & 1), By = 2 * Qy + ((b >> 1) & 1), Bz = 2 * Qz + (b >> 2);
             for (int i = 0; i < nP; ++i) {
                 const char4 P = p.plist_near[i];
                 const int Ax = Bx + P.x, Ay = By + P.y, Az = Bz + P.z;
-                if ((P.x == 0 && P.y == 0 && P.z == 0) || Ax < 0 || Ay < 0 || Az < 0 || (Ax >> 3) >= m ||
-                    (Ay >> 3) >= m || (Az >> 3) >= m)
+                // A's sub-grid among the 27 around this lane's (out of the domain: never refined)
+                const int e = ((Az >> 3) - sgz + 1) * 9 + ((Ay >> 3) - sgy + 1) * 3 + ((Ax >> 3) - sgx + 1);
+                if ((P.x == 0 && P.y == 0 && P.z == 0) || Ax < 0 || Ay < 0 || Az < 0 || !((refined >> e) & 1u))
                     continue;
-                if (nt[((int64_t)(Az >> 3) * m + (Ay >> 3)) * m + (Ax >> 3)] != 2) continue;
                 for (int c = 0; c < 8; ++c) {
                     const int64_t si = src_index(2 * Ax + (c & 1), 2 * Ay + ((c >> 1) & 1), 2 * Az + (c >> 2),
                                                  p.hp_dn, p.pp_dn, 0);
