@@ -265,33 +265,53 @@ void leaf_tables(const std::vector<double> &Ktab, const std::vector<char4> &pl, 
                 Ksa[((size_t)j * nP + i) * 27 + e] = (j == 0 ? 1.0 : -1.0) * Kst[(i * 27 + e) * 4 + j];
 }
 
-// Coarse-fine kernel rows [near offset][child][K0, K1x, K1y, K1z] for source
-// offsets D = (2 o + sgn (c - 1/2)) h per axis, D = source - sink:
-//   up (sgn = -1): sink = child c of parent Q, source = cell Q + o one level up
-//   down (sgn = +1): sink = a cell B, source = child c of cell B + o one level down
+// Coarse-fine kernel row (K0, K1x, K1y, K1z) for the source offset
+// D = (2 o + sgn (c - 1/2)) h per axis, D = source - sink, c a child index
+void cf_row(const int o[3], int c, int sgn, double h, double G, double *row)
+{
+    double D[3];
+    for (int k = 0; k < 3; ++k) D[k] = (2.0 * o[k] + sgn * (((c >> k) & 1) - 0.5)) * h;
+    const double r = std::sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    row[0] = -G / r;
+    for (int k = 0; k < 3; ++k) row[1 + k] = G * D[k] / (r * r * r);
+}
+
+// up: [near offset][child c][4], sink = child c of parent Q, source = cell
+// Q + o one level up (sgn = -1)
 void cf_table(const std::vector<char4> &pl, double h, double G, int sgn, std::vector<double> &K)
 {
     K.assign(pl.size() * 8 * 4, 0.0);
     for (size_t i = 0; i < pl.size(); ++i) {
         if (!pl[i].x && !pl[i].y && !pl[i].z) continue;
         const int o[3] = {pl[i].x, pl[i].y, pl[i].z};
-        for (int c = 0; c < 8; ++c) {
-            double D[3];
-            for (int k = 0; k < 3; ++k) D[k] = (2.0 * o[k] + sgn * (((c >> k) & 1) - 0.5)) * h;
-            const double r = std::sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-            double *row = &K[(i * 8 + c) * 4];
-            row[0] = -G / r;
-            for (int k = 0; k < 3; ++k) row[1 + k] = G * D[k] / (r * r * r);
-        }
+        for (int c = 0; c < 8; ++c) cf_row(o, c, sgn, h, G, &K[(i * 8 + c) * 4]);
     }
 }
 
-// Blocks (64 parents, the leaf pass's grouping) of level l's leaf pass that
-// hold a parent of a listed sub-grid's cells
-std::vector<int32_t> blocks_of(int l, const std::vector<int32_t> &nodes)
+// down: [o in [-3, 3]^3][child c][4], sink = a cell B, source = child c of
+// the cell B + o one level down (sgn = +1); zero unless 0 < |o|^2 <= r2i
+void cf_table_down(int r2i, double h, double G, std::vector<double> &K)
+{
+    K.assign(343 * 8 * 4, 0.0);
+    for (int i = 0; i < 343; ++i) {
+        const int o[3] = {i % 7 - 3, (i / 7) % 7 - 3, i / 49 - 3};
+        const int o2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+        if (o2 == 0 || o2 > r2i) continue;
+        for (int c = 0; c < 8; ++c) cf_row(o, c, +1, h, G, &K[((size_t)i * 8 + c) * 4]);
+    }
+}
+
+// Block shape of an adaptive tree's level l (np = 4 << l parents per axis,
+// the grid of its M2L and of its leaf pass): one sub-grid per block from 64
+// parents per axis on (levels 4 and deeper, sparse), rows below
+Block amr_block(int l) { return block_shape(4 << l, (4 << l) >= 64); }
+
+// Blocks (64 parents of shape bs) of level l that hold a parent of a listed
+// sub-grid's cells
+std::vector<int32_t> blocks_of(int l, const std::vector<int32_t> &nodes, Block bs)
 {
     const int np = 4 << l;
-    const int bx = std::min(np, 64), by = std::min(np, 64 / bx), bz = 64 / (bx * by);
+    const int bx = bs.bx, by = bs.by, bz = bs.bz;
     const int nbx = np / bx, nby = np / by;
     std::vector<int32_t> out;
     for (int32_t pk : nodes) {
@@ -313,13 +333,13 @@ void build_amr_tables(ot_fmm_plan P)
     for (int l = 1; l <= L; ++l) {
         P->lblk[l].clear();
         if (P->lnodes[l].empty()) continue;
-        P->lblk[l] = blocks_of(l, P->lnodes[l]);
+        P->lblk[l] = blocks_of(l, P->lnodes[l], amr_block(l));
         const double hl = P->h * (double)(1 << (L - l)), r = P->h / hl;
         leaf_tables(P->Ktab, P->plist_near, r, r * r, r2i, l < L, P->Kst_l[l], P->Ksa_l[l]);
         P->Kup_l[l].clear();
         P->Kdn_l[l].clear();
         if (!P->lnodes[l - 1].empty()) cf_table(P->plist_near, hl, P->G, -1, P->Kup_l[l]);
-        if (l < L && !P->lnodes[l + 1].empty()) cf_table(P->plist_near, 0.5 * hl, P->G, +1, P->Kdn_l[l]);
+        if (l < L && !P->lnodes[l + 1].empty()) cf_table_down(r2i, 0.5 * hl, P->G, P->Kdn_l[l]);
     }
 }
 
@@ -402,9 +422,9 @@ void build_tables(ot_fmm_plan P)
 // per axis has a source in the domain: the block's parents shifted by P
 // overlap [0, np) on every axis.  The blocks are those of the kernels: 64
 // parents, bx * by * bz, numbered x fastest.
-bool unit_has_sources(int np, int blk, char4 P)
+bool unit_has_sources(int np, int blk, char4 P, Block bs)
 {
-    const int bx = std::min(np, 64), by = std::min(np, 64 / bx), bz = 64 / (bx * by);
+    const int bx = bs.bx, by = bs.by, bz = bs.bz;
     const int nbx = np / bx, nby = np / by;
     const int x0 = (blk % nbx) * bx, y0 = ((blk / nbx) % nby) * by, z0 = (blk / (nbx * nby)) * bz;
     auto overlap = [np](int a0, int n, int o) { return a0 + o < np && a0 + n - 1 + o >= 0; };
@@ -440,10 +460,11 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
             std::vector<int32_t> all(P->lnodes[l]);
             all.insert(all.end(), P->rnodes[l].begin(), P->rnodes[l].end());
             live.assign((size_t)(U[l] / nP), 0);
-            for (int32_t b : blocks_of(l, all)) live[(size_t)b] = 1;
+            for (int32_t b : blocks_of(l, all, amr_block(l))) live[(size_t)b] = 1;
         }
+        const Block bs = P->amr ? amr_block(l) : block_shape(np);
         for (int64_t u = 0; u < U[l]; ++u)
-            if (unit_has_sources(np, (int)(u / nP), pl[u % nP]) && (live.empty() || live[(size_t)(u / nP)])) {
+            if (unit_has_sources(np, (int)(u / nP), pl[u % nP], bs) && (live.empty() || live[(size_t)(u / nP)])) {
                 pos[l].push_back(u);
             }
         V[l] = (int64_t)pos[l].size();
@@ -769,6 +790,7 @@ int setup_amr_views(ot_fmm_plan P)
         v.src = srcs[l];
         v.own_pieces = l < L ? 1 : 0;
         v.ntype_L = P->dev_ntype[l];
+        v.leaf_subgrid_blocks = (4 << l) >= 64;      // as amr_block(l)
         if ((rc = dev_upload(P, &v.blist, P->lblk[l]))) return rc;
         v.nblist = (int)P->lblk[l].size();
         v.Kcf_up = v.Kcf_dn = nullptr;
@@ -838,9 +860,10 @@ int setup_device(ot_fmm_plan P)
         v.hp = (l == 0) ? 3 : 2;
         v.pp = v.np + 2 * v.hp;
         v.h = P->h * (double)(1 << (L - l));
-        v.bx = std::min(v.np, 64);
-        v.by = std::min(v.np, 64 / v.bx);
-        v.bz = 64 / (v.bx * v.by);
+        const Block bs = P->amr ? amr_block(l) : block_shape(v.np);
+        v.bx = bs.bx;
+        v.by = bs.by;
+        v.bz = bs.bz;
         v.nbx = v.np / v.bx;
         v.nby = v.np / v.by;
         const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;

@@ -48,6 +48,24 @@ __host__ __device__ inline int off_index(int ox, int oy, int oz)
     return ((oz + OFF_R) * OFF_W + (oy + OFF_R)) * OFF_W + (ox + OFF_R);
 }
 
+// 64 lanes of a wave cover a block of bx*by*bz parents of an np^3 grid:
+// rows along x (as long as np allows), or, with subgrid, the 4x4x4 parents of
+// one sub-grid (sparse levels of adaptive trees, where rows would hold cells
+// of sub-grids that do not exist)
+struct Block { int bx, by, bz; };
+__host__ __device__ inline Block block_shape(int np, int subgrid = 0)
+{
+    Block b;
+    if (subgrid) {
+        b.bx = b.by = b.bz = 4;
+        return b;
+    }
+    b.bx = np < 64 ? np : 64;
+    b.by = np < 64 / b.bx ? np : 64 / b.bx;
+    b.bz = 64 / (b.bx * b.by);
+    return b;
+}
+
 struct DevLevel {
     int np;          // parents per axis (n_l / 2)
     int hp;          // halo of the moment array, in parents
@@ -116,10 +134,12 @@ struct DevPlan {
     int own_pieces;              // leaf cells of this level are M2L sinks too (levels below the finest)
     const int32_t *blist; int nblist;   // blocks of the leaf pass holding a leaf sub-grid of this level
     const uint8_t *ntype_L;             // kinds of this level's sub-grids (0 none, 1 leaf, 2 refined)
+    int leaf_subgrid_blocks;            // blocks of the leaf pass are sub-grids (block_shape)
     const double *src_up, *src_dn;      // source planes of levels L-1 and L+1 (null without leaves there)
     int hp_up, pp_up, hp_dn, pp_dn;
     const double *Kcf_up;        // [n_plist_near][8][4]: kernel rows, child c of a parent to a leaf of level L-1
-    const double *Kcf_dn;        // [n_plist_near][8][4]: kernel rows, cell of level L to child c' of a level-L cell
+    const double *Kcf_dn;        // [7^3][8][4]: kernel rows, cell of level L to child c' of the level-L cell
+                                 //   at offset o in [-3, 3]^3 (zero rows where o = 0 or |o|^2 > r2i)
     DevLevel lev[MAX_LEVELS];
 };
 

@@ -316,17 +316,6 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
     return (bid & 7) * per + (bid >> 3);
 }
 
-// 64 lanes of a wave cover a block of bx*by*bz parents of an np^3 grid
-struct Block { int bx, by, bz; };
-__host__ __device__ inline Block block_shape(int np)
-{
-    Block b;
-    b.bx = np < 64 ? np : 64;
-    b.by = np < 64 / b.bx ? np : 64 / b.bx;
-    b.bz = 64 / (b.bx * b.by);
-    return b;
-}
-
 // ------------------------------------------------------------------------
 // P2M and the first M2M, for one leaf parent Q (a cell of level L-1): stages
 // Q's 8 leaf sources into the padded source planes and returns Q's scaled
@@ -1096,7 +1085,7 @@ __global__ __launch_bounds__(LEAF_MAX_CHUNKS * 64) void k_leaf(const DevPlan p, 
                                                               int nchunk)
 {
     const int npL = p.npL;
-    const Block bs = block_shape(npL);
+    const Block bs = block_shape(npL, p.leaf_subgrid_blocks);
     const int nbx = npL / bs.bx, nby = npL / bs.by, nbz = npL / bs.bz;
     const int bi = xcd_remap(blockIdx.x, gridDim.x);
     const int blk = p.blist ? (bi < p.nblist ? p.blist[bi] : -1) : bi;
@@ -1397,7 +1386,7 @@ template <bool ADJ>
 __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restrict__ out0, double *__restrict__ out1)
 {
     const int npL = p.npL;
-    const Block bs = block_shape(npL);
+    const Block bs = block_shape(npL, p.leaf_subgrid_blocks);
     const int nbx = npL / bs.bx, nby = npL / bs.by;
     if ((int)blockIdx.x >= p.nblist) return;
     const int blk = p.blist[blockIdx.x];
@@ -1471,21 +1460,48 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
         }
     }
     if (p.src_dn && refined) {
-        const int64_t pl = 8 * (int64_t)p.pp_dn * p.pp_dn * p.pp_dn;
+        // the cells A = 2Q + d, d in [-2, 3]^3, around this lane's 8 children
+        // B = 2Q + b hold every near partner; where A is refined, its 8
+        // children (leaves one level finer) are loaded once and paired with
+        // each child B that A is near to (o = A - B)
+        const int64_t pp = p.pp_dn, pp3 = pp * pp * pp;
+        const double2 *__restrict__ S2 = reinterpret_cast<const double2 *>(p.src_dn);
+        constexpr int NPL = ADJ ? 4 : 1;     // source planes
+        for (int d = 0; d < 216; ++d) {
+            const int dx = d % 6 - 2, dy = (d / 6) % 6 - 2, dz = d / 36 - 2;
+            const int Ax = 2 * Qx + dx, Ay = 2 * Qy + dy, Az = 2 * Qz + dz;
+            const int e = ((Az >> 3) - sgz + 1) * 9 + ((Ay >> 3) - sgy + 1) * 3 + ((Ax >> 3) - sgx + 1);
+            if (Ax < 0 || Ay < 0 || Az < 0 || !((refined >> e) & 1u)) continue;
+            const int64_t pad = ((int64_t)(Az + p.hp_dn) * pp + (Ay + p.hp_dn)) * pp + (Ax + p.hp_dn);
+            double mc[NPL][8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int Bx = 2 * Qx + (b & 1), By = 2 * Qy + ((b >> 1) & 1), Bz = 2 * Qz + (b >> 2);
-            for (int i = 0; i < nP; ++i) {
-                const char4 P = p.plist_near[i];
-                const int Ax = Bx + P.x, Ay = By + P.y, Az = Bz + P.z;
-                // A's sub-grid among the 27 around this lane's (out of the domain: never refined)
-                const int e = ((Az >> 3) - sgz + 1) * 9 + ((Ay >> 3) - sgy + 1) * 3 + ((Ax >> 3) - sgx + 1);
-                if ((P.x == 0 && P.y == 0 && P.z == 0) || Ax < 0 || Ay < 0 || Az < 0 || !((refined >> e) & 1u))
-                    continue;
+            for (int j = 0; j < NPL; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double2 v = S2[(int64_t)j * 4 * pp3 + c * pp3 + pad];
+                    mc[j][2 * c] = v.x;
+                    mc[j][2 * c + 1] = v.y;
+                }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int ox = dx - (b & 1), oy = dy - ((b >> 1) & 1), oz = dz - (b >> 2);
+                const int o2 = ox * ox + oy * oy + oz * oz;
+                if (o2 == 0 || o2 > p.r2i) continue;
+                const double *K = p.Kcf_dn + (int64_t)(((oz + 3) * 7 + (oy + 3)) * 7 + (ox + 3)) * 32;
+#pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    const int64_t si = src_index(2 * Ax + (c & 1), 2 * Ay + ((c >> 1) & 1), 2 * Az + (c >> 2),
-                                                 p.hp_dn, p.pp_dn, 0);
-                    pair(acc[b], p.Kcf_dn + ((int64_t)i * 8 + c) * 4, p.src_dn, si, pl);
+                    const double *k = K + 4 * c;
+                    if constexpr (!ADJ) {
+                        acc[b][0] = fma(k[0], mc[0][c], acc[b][0]);
+                        acc[b][1 % NA] = fma(k[1], mc[0][c], acc[b][1 % NA]);
+                        acc[b][2 % NA] = fma(k[2], mc[0][c], acc[b][2 % NA]);
+                        acc[b][3 % NA] = fma(k[3], mc[0][c], acc[b][3 % NA]);
+                    } else {
+                        acc[b][0] = fma(k[0], mc[0][c], acc[b][0]);
+                        acc[b][0] = fma(-k[1], mc[NPL > 1 ? 1 : 0][c], acc[b][0]);
+                        acc[b][0] = fma(-k[2], mc[NPL > 2 ? 2 : 0][c], acc[b][0]);
+                        acc[b][0] = fma(-k[3], mc[NPL > 3 ? 3 : 0][c], acc[b][0]);
+                    }
                 }
             }
         }
@@ -1591,7 +1607,7 @@ hipError_t launch_l2l_span(const DevPlan &p, int i, hipStream_t s)
 hipError_t launch_leaf_chunks(const DevPlan &p, int adj, int nchunk, double *out0, double *out1, hipStream_t s)
 {
     if (nchunk < 1 || nchunk > LEAF_MAX_CHUNKS) return hipErrorInvalidValue;
-    const Block bs = block_shape(p.npL);
+    const Block bs = block_shape(p.npL, p.leaf_subgrid_blocks);
     const int64_t nblk = p.blist ? (int64_t)p.nblist : ((int64_t)p.npL / bs.bx) * (p.npL / bs.by) * (p.npL / bs.bz);
     if (nblk == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nblk + 7) / 8 * 8);               // whole rounds over the 8 XCDs
