@@ -919,9 +919,12 @@ __global__ __launch_bounds__(L2L_SPAN_WG) void k_l2l_span(const DevPlan p, int l
     const int lv = ltop + j;
     int cx, cy, cz;
     span_cell(ax, ay, az, j, ci, cx, cy, cz);
-    if (act && p.lev[lv].ntype) {        // adaptive tree: only cells of existing sub-grids
+    if (act && p.lev[lv].ntype) {
+        // adaptive tree: only cells of refined sub-grids.  A leaf cell's final
+        // expansion has no reader: it has no children, and the leaf passes
+        // form their locals from the parent level and the cell's own pieces.
         const int64_t m = (int64_t)1 << lv;
-        act = p.lev[lv].ntype[((int64_t)(cz >> 3) * m + (cy >> 3)) * m + (cx >> 3)] != 0;
+        act = p.lev[lv].ntype[((int64_t)(cz >> 3) * m + (cy >> 3)) * m + (cx >> 3)] == 2;
     }
     const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
     double C[NC];
@@ -1382,27 +1385,32 @@ __device__ __forceinline__ int64_t src_index(int x, int y, int z, int hp, int pp
 // M2L expansion at its centre (potential, minus the gradient).  Coarse-fine
 // P2P, up: the leaves of level L-1 near Q; down: the children (leaves of
 // level L+1) of the refined cells near each child.
+// A block's CF_WAVES waves split the loops (wave 0 also the own pieces) and
+// meet in LDS in the fixed order ((w1 + w2) + ...) + w0.
+constexpr int CF_WAVES = 8;
 template <bool ADJ>
-__global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restrict__ out0, double *__restrict__ out1)
+__global__ __launch_bounds__(CF_WAVES * 64) void k_amr_cf(const DevPlan p, double *__restrict__ out0,
+                                                         double *__restrict__ out1)
 {
     const int npL = p.npL;
     const Block bs = block_shape(npL, p.leaf_subgrid_blocks);
     const int nbx = npL / bs.bx, nby = npL / bs.by;
-    if ((int)blockIdx.x >= p.nblist) return;
+    if ((int)blockIdx.x >= p.nblist) return;        // the whole workgroup
     const int blk = p.blist[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform(threadIdx.x >> 6);
     const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
     const int Qy = ((blk / nbx) % nby) * bs.by + (lane / bs.bx) % bs.by;
     const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
     const int32_t slot = p.leaf_slot[((int64_t)(Qz >> 2) * p.sL + (Qy >> 2)) * p.sL + (Qx >> 2)];
-    if (slot < 0) return;
+    const bool live = slot >= 0;           // lanes of other sub-grids still meet the barriers
     constexpr int NA = ADJ ? 1 : 4;
     double acc[8][NA];
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
         for (int a = 0; a < NA; ++a) acc[b][a] = 0.0;
-    if (p.own_pieces) {
+    if (live && wave == 0 && p.own_pieces) {
         const DevLevel &D = p.lev[p.L];
         const int64_t nq = D.np, nq3 = nq * nq * nq;
         const int64_t q = ((int64_t)Qz * nq + Qy) * nq + Qx;
@@ -1426,7 +1434,7 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
     const int64_t m = p.sL;
     const int sgx = Qx >> 2, sgy = Qy >> 2, sgz = Qz >> 2;
     uint32_t refined = 0, missing = 0;
-    for (int e = 0; e < 27; ++e) {
+    for (int e = 0; e < 27 && live; ++e) {
         const int x = sgx + e % 3 - 1, y = sgy + (e / 3) % 3 - 1, z = sgz + e / 9 - 1;
         if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) continue;
         const uint8_t t = p.ntype_L[((int64_t)z * m + y) * m + x];
@@ -1451,7 +1459,7 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
     };
     if (p.src_up && missing) {
         const int64_t pl = 8 * (int64_t)p.pp_up * p.pp_up * p.pp_up;
-        for (int i = 0; i < nP; ++i) {
+        for (int i = wave * nP / CF_WAVES; i < (wave + 1) * nP / CF_WAVES; ++i) {
             const char4 P = p.plist_near[i];
             if (P.x == 0 && P.y == 0 && P.z == 0) continue;
             const int64_t si = src_index(Qx + P.x, Qy + P.y, Qz + P.z, p.hp_up, p.pp_up, 0);
@@ -1467,7 +1475,7 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
         const int64_t pp = p.pp_dn, pp3 = pp * pp * pp;
         const double2 *__restrict__ S2 = reinterpret_cast<const double2 *>(p.src_dn);
         constexpr int NPL = ADJ ? 4 : 1;     // source planes
-        for (int d = 0; d < 216; ++d) {
+        for (int d = wave * 216 / CF_WAVES; d < (wave + 1) * 216 / CF_WAVES; ++d) {
             const int dx = d % 6 - 2, dy = (d / 6) % 6 - 2, dz = d / 36 - 2;
             const int Ax = 2 * Qx + dx, Ay = 2 * Qy + dy, Az = 2 * Qz + dz;
             const int e = ((Az >> 3) - sgz + 1) * 9 + ((Ay >> 3) - sgy + 1) * 3 + ((Ax >> 3) - sgx + 1);
@@ -1506,6 +1514,21 @@ __global__ __launch_bounds__(64) void k_amr_cf(const DevPlan p, double *__restri
             }
         }
     }
+    __shared__ double red[8 * NA][64];      // running sum of waves 1 .. c
+    for (int c = 1; c < CF_WAVES; ++c) {
+        if (wave == c) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+#pragma unroll
+                for (int a = 0; a < NA; ++a) red[b * NA + a][lane] = (c == 1) ? acc[b][a] : red[b * NA + a][lane] + acc[b][a];
+        }
+        __syncthreads();
+    }
+    if (wave != 0 || !live) return;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) acc[b][a] += red[b * NA + a][lane];
     const int64_t base = (int64_t)slot * 512;
     const int lx0 = (2 * Qx) & 7, ly0 = (2 * Qy) & 7, lz0 = (2 * Qz) & 7;
     const int64_t N = p.n_leaf_cells;
@@ -1663,9 +1686,9 @@ hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, 
 {
     if (v.nblist <= 0 || (!v.own_pieces && !v.src_up && !v.src_dn)) return hipSuccess;
     if (adj)
-        hipLaunchKernelGGL(k_amr_cf<true>, dim3(v.nblist), dim3(64), 0, s, v, out0, out1);
+        hipLaunchKernelGGL(k_amr_cf<true>, dim3(v.nblist), dim3(CF_WAVES * 64), 0, s, v, out0, out1);
     else
-        hipLaunchKernelGGL(k_amr_cf<false>, dim3(v.nblist), dim3(64), 0, s, v, out0, out1);
+        hipLaunchKernelGGL(k_amr_cf<false>, dim3(v.nblist), dim3(CF_WAVES * 64), 0, s, v, out0, out1);
     return hipGetLastError();
 }
 
