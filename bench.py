@@ -15,7 +15,7 @@ pass), timed by HIP events around its launches inside the timed region, against
 the FP64 vector peak of the MI355X.  `cpu_baseline` times the CPU
 oracle (forward + adjoint) on a z-slab of the same workload.  `m2l_fp32` times
 the FP32 M2L plan on the same workload; `batch` times 16 independent small
-octrees plan by plan, as one batch over 4 streams and as HIP graph replays;
+adaptive octrees plan by plan, as one batch over 4 streams and as HIP graph replays;
 `amr` times the adaptive-octree workload (leaves on levels 3..6 of a 512^3
 box) and, in the CPU-baseline leg, checks sampled cells against the oracle.
 """
@@ -87,10 +87,11 @@ def phase_flops(phase: str, info: dict) -> float:
 
 
 def bench_batch(args) -> dict:
-    """16 independent octrees (leaf counts log-uniform in [64, 1024], seed 3,
-    as uniform trees of depth 2 or 3): forward + adjoint of all of them per
-    step, plan by plan on one stream, as one batch over 4 streams, and as the
-    replay of that batch captured in two HIP graphs."""
+    """16 independent adaptive octrees (leaf sub-grid targets log-uniform in
+    [64, 1024], seed 3, grown by density-ranked refinement and balanced 2:1):
+    forward + adjoint of all of them per step, plan by plan on one stream, as
+    one batch over 4 streams, and as the replay of that batch captured in two
+    HIP graphs."""
     import numpy as np
     import torch
 
@@ -99,11 +100,10 @@ def bench_batch(args) -> dict:
     plans, rhos, ws, us, phis, gs, drhos = [], [], [], [], [], [], []
     pairs = 0
     for t in trees:
-        lay = W.uniform_layout(t["L"])
-        p = fmm.Plan(lay)
+        p = fmm.Plan(t["layout"])
         inf = p.info()
         pairs += 2 * (inf["p2p_pairs"] + inf["m2l_pairs"])
-        dev = lambda a, lay=lay: torch.from_numpy(lay.dense_to_layout(np.ascontiguousarray(a))).cuda()  # noqa: E731
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
         plans.append(p)
         rhos.append(dev(t["rho"]))
         ws.append(dev(t["w"]))
@@ -148,9 +148,10 @@ def bench_batch(args) -> dict:
     b.close()
     log(f"batch of {len(trees)} trees: single {res['single']:.3f} ms, batch {res['batch']:.3f} ms, "
         f"graph {res['graph']:.3f} ms per step")
-    return {"workload": f"{len(trees)} octrees, leaf counts log-uniform in [64, 1024] (seed 3) as uniform trees "
-                        f"of depth {sorted(set(t['L'] for t in trees))}, "
-                        f"{sum(8 ** t['L'] for t in trees)} sub-grids; one step = forward + adjoint of every tree",
+    return {"workload": f"{len(trees)} adaptive octrees, leaf sub-grid targets log-uniform in [64, 1024] (seed 3), "
+                        f"grown by density-ranked refinement of a sphere or polytrope, 2:1 balanced, depths "
+                        f"{sorted(set(t['layout'].depth for t in trees))}, {sum(t['n_leaf'] for t in trees)} leaf "
+                        f"sub-grids; one step = forward + adjoint of every tree",
             "steps": k, "streams": ns, "cell_interactions_per_step": pairs,
             "ms_per_step": res, "cell_interactions_per_s_graph": pairs / (res["graph"] * 1e-3),
             "speedup_graph_vs_single": res["single"] / res["graph"],

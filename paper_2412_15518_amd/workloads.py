@@ -238,32 +238,63 @@ def cfg5_lognormal(n: int = 64, seed: int = 5, n_fd: int = 64):
     return dict(L=L, rho=rho, w=w, u=u, cells=cells)
 
 
-def batch_of_octrees(count: int = 16, seed: int = 3, lo: int = 64, hi: int = 1024):
-    """Independent octrees for the batched path: leaf sub-grid counts drawn
-    log-uniform in [lo, hi], each rounded in log scale to the uniform tree with
-    8^L leaf sub-grids (the library's octrees have all leaves on one level, so
-    [64, 1024] gives L = 2 or 3).  Each tree holds either a uniform sphere or an
-    n = 1.5 polytrope at a random centre, on a 1e-10 floor, plus cotangents
-    w, u ~ N(0,1).  Drawn in the order: counts, then per tree kind, centre,
+def batch_of_octrees(count: int = 16, seed: int = 3, lo: int = 64, hi: int = 1024, Lcap: int = 4):
+    """Independent adaptive octrees for the batched path.  Leaf sub-grid targets
+    are drawn log-uniform in [lo, hi]; each tree holds a uniform sphere or an
+    n = 1.5 polytrope (random centre, radius, rho_c) on a 1e-10 floor in a box of
+    8 * 2^Lcap cells of the deepest allowed level, and grows from its root by
+    density-ranked refinement: each round refines the leaves of highest peak
+    density at their cell centres (ties: coarser level, then nearer the star's
+    centre), then balances the tree 2:1, until the leaf count reaches the
+    target.  rho (at the leaf cell centres) and cotangents w, u ~ N(0,1) are in
+    layout order.  Drawn in the order: targets, then per tree kind, centre,
     radius, rho_c, w, u."""
     rng = np.random.default_rng(seed)
     counts = np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))
+    box = float(SUBGRID << Lcap)
+    l8 = np.arange(SUBGRID, dtype=np.float64)
+    lz, ly, lx = np.meshgrid(l8, l8, l8, indexing="ij")
+    loc = np.stack([lx.ravel(), ly.ravel(), lz.ravel()], axis=1) + 0.5
     trees = []
     for c in counts:
-        L = max(1, int(round(math.log(c) / math.log(8.0))))
-        n = SUBGRID << L
+        target = int(round(c))
         kind = "sphere" if rng.uniform() < 0.5 else "polytrope"
-        centre = tuple(rng.uniform(0.3 * n, 0.7 * n, size=3))
-        radius = float(rng.uniform(0.15 * n, 0.35 * n))
+        centre = rng.uniform(0.3 * box, 0.7 * box, size=3)
+        radius = float(rng.uniform(0.15 * box, 0.35 * box))
         rho_c = float(rng.uniform(0.5, 1.0))
-        if kind == "sphere":
-            rho = uniform_sphere(n, radius, centre, rho_c)
-        else:
-            rho = polytrope(n, centre, radius, rho_c)
-        rho = rho + 1e-10
-        w = rng.standard_normal((n, n, n))
-        u = rng.standard_normal((3, n, n, n))
-        trees.append(dict(L=L, n=n, kind=kind, leaf_count=float(c), rho=rho, w=w, u=u))
+
+        def rho_at(pts, kind=kind, centre=centre, radius=radius, rho_c=rho_c):
+            if kind == "sphere":
+                r = np.sqrt(((pts - centre) ** 2).sum(axis=-1))
+                return np.where(r <= radius, rho_c, 0.0) + 1e-10
+            return _polytrope_at(pts, centre, radius, rho_c) + 1e-10
+
+        refined = [set() for _ in range(Lcap)]
+        leaves = [(0, (0, 0, 0))]
+        while len(leaves) < target:
+            cand = [(l, q) for (l, q) in leaves if l < Lcap]
+            if not cand:
+                break
+            lv = np.array([l for l, _ in cand], dtype=np.float64)
+            cq = np.array([q for _, q in cand], dtype=np.float64)
+            hl = 2.0 ** (Lcap - lv)
+            pts = (cq[:, None, :] * SUBGRID + loc[None]) * hl[:, None, None]
+            peak = rho_at(pts).max(axis=1)
+            dist = np.sqrt((((cq + 0.5) * SUBGRID * hl[:, None] - centre) ** 2).sum(axis=1))
+            order = np.lexsort((dist, lv, -peak))
+            k = max(1, int(math.ceil((target - len(leaves)) / 14.0)))
+            for i in order[:k]:
+                refined[int(lv[i])].add(tuple(int(v) for v in cq[i]))
+            _balance(refined, Lcap)
+            lay = _layout_of(refined, Lcap, 1.0, 1.0)
+            leaves = [(int(lay.level[i]), tuple(int(v) for v in lay.coord[i])) for i in lay.leaf_nodes]
+        lay = _layout_of(refined, Lcap, 1.0, 1.0)
+        centres, _ = leaf_cell_centres(lay)        # box units: the tree's h_leaf_min is 2^(Lcap - depth)
+        rho = rho_at(centres)
+        w = rng.standard_normal(lay.n_leaf_cells)
+        u = rng.standard_normal((3, lay.n_leaf_cells))
+        trees.append(dict(layout=lay, kind=kind, leaf_count=float(c), target=target,
+                          n_leaf=int(lay.is_leaf.sum()), rho=rho, w=w, u=u))
     return trees
 
 
@@ -289,25 +320,10 @@ _NEIGHBOURS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in 
                if (dx, dy, dz) != (0, 0, 0)]
 
 
-def adaptive_layout(Lmax: int, refine, base: int = 0, h: float = 1.0, G: float = 1.0) -> Layout:
-    """Octree refined top-down: every node above level `base` is refined, and a
-    node of level l in [base, Lmax) is refined where refine(l, coords) says so
-    (coords: int array [k, 3] of sub-grid coordinates; returns bool [k]).  The
-    tree is then balanced 2:1: wherever a node of level l is refined, the 26
-    nodes around it at level l exist (refining their parents as needed), so
-    leaf sub-grids that touch lie at most one level apart.  Nodes are listed
-    level by level, z-major inside a level; h is the finest level's cell width."""
-    if Lmax < 0 or not 0 <= base <= Lmax:
-        raise ValueError("need 0 <= base <= Lmax")
-    refined = [set() for _ in range(Lmax)]
-    nodes = {(0, 0, 0)}
-    for l in range(Lmax):
-        cur = sorted(nodes)
-        arr = np.array(cur, dtype=np.int64).reshape(-1, 3)
-        want = np.ones(len(cur), dtype=bool) if l < base else np.asarray(refine(l, arr), dtype=bool)
-        refined[l] = {c for c, w in zip(cur, want) if w}
-        nodes = {(2 * x + (b & 1), 2 * y + ((b >> 1) & 1), 2 * z + (b >> 2))
-                 for (x, y, z) in refined[l] for b in range(8)}
+def _balance(refined: list, Lmax: int) -> None:
+    """2:1 balance in place: wherever a node of level l is refined, the 26
+    nodes around it at level l must exist, so their parents are refined (and
+    so on up the levels)."""
     changed = True
     while changed:
         changed = False
@@ -322,6 +338,11 @@ def adaptive_layout(Lmax: int, refine, base: int = 0, h: float = 1.0, G: float =
                     if par not in refined[l - 1]:
                         refined[l - 1].add(par)
                         changed = True
+
+
+def _layout_of(refined: list, Lmax: int, h: float, G: float) -> Layout:
+    """The octree whose refined nodes per level are `refined` (every refined
+    node's parent refined), listed level by level, z-major inside a level."""
     levels, coords, leaf = [], [], []
     cur = [(0, 0, 0)]
     for l in range(Lmax + 1):
@@ -333,15 +354,44 @@ def adaptive_layout(Lmax: int, refine, base: int = 0, h: float = 1.0, G: float =
         if l < Lmax:
             cur = [(2 * x + (b & 1), 2 * y + ((b >> 1) & 1), 2 * z + (b >> 2))
                    for (x, y, z) in cur if (x, y, z) in refined[l] for b in range(8)]
+    depth = max([l for l in range(Lmax) if refined[l]], default=-1) + 1
     level = np.array(levels, dtype=np.int32)
     coord = np.array(coords, dtype=np.int32).reshape(-1, 3)
+    keep = level <= depth
+    level, coord = level[keep], coord[keep]
+    is_leaf = np.array(leaf, dtype=np.uint8)[keep]
+    is_leaf[level == depth] = 1
     pos = {(int(l), int(c[0]), int(c[1]), int(c[2])): i for i, (l, c) in enumerate(zip(level, coord))}
     parent = np.full(level.shape[0], -1, dtype=np.int32)
     for i, (l, c) in enumerate(zip(level, coord)):
         if l > 0:
             parent[i] = pos[(int(l) - 1, int(c[0]) >> 1, int(c[1]) >> 1, int(c[2]) >> 1)]
-    return Layout(level=level, coord=coord, parent=parent, is_leaf=np.array(leaf, dtype=np.uint8),
-                  h_leaf_min=h, G=G)
+    return Layout(level=level, coord=coord, parent=parent, is_leaf=is_leaf,
+                  h_leaf_min=h * 2.0 ** (Lmax - depth), G=G)
+
+
+def adaptive_layout(Lmax: int, refine, base: int = 0, h: float = 1.0, G: float = 1.0) -> Layout:
+    """Octree refined top-down: every node above level `base` is refined, and a
+    node of level l in [base, Lmax) is refined where refine(l, coords) says so
+    (coords: int array [k, 3] of sub-grid coordinates; returns bool [k]).  The
+    tree is then balanced 2:1: wherever a node of level l is refined, the 26
+    nodes around it at level l exist (refining their parents as needed), so
+    leaf sub-grids that touch lie at most one level apart.  Nodes are listed
+    level by level, z-major inside a level; h is the cell width of level Lmax
+    (the tree's own finest level may be coarser)."""
+    if Lmax < 0 or not 0 <= base <= Lmax:
+        raise ValueError("need 0 <= base <= Lmax")
+    refined = [set() for _ in range(Lmax)]
+    nodes = {(0, 0, 0)}
+    for l in range(Lmax):
+        cur = sorted(nodes)
+        arr = np.array(cur, dtype=np.int64).reshape(-1, 3)
+        want = np.ones(len(cur), dtype=bool) if l < base else np.asarray(refine(l, arr), dtype=bool)
+        refined[l] = {c for c, w in zip(cur, want) if w}
+        nodes = {(2 * x + (b & 1), 2 * y + ((b >> 1) & 1), 2 * z + (b >> 2))
+                 for (x, y, z) in refined[l] for b in range(8)}
+    _balance(refined, Lmax)
+    return _layout_of(refined, Lmax, h, G)
 
 
 def leaf_cell_centres(layout: Layout) -> tuple:

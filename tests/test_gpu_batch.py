@@ -36,11 +36,11 @@ def trees():
     ts = W.batch_of_octrees()
     out = []
     for t in ts:
-        lay = W.uniform_layout(t["L"])
-        dev = lambda a, lay=lay: torch.from_numpy(lay.dense_to_layout(np.ascontiguousarray(a))).cuda()  # noqa: E731
+        lay = t["layout"]
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
         out.append(dict(t, lay=lay, plan=fmm.Plan(lay), rho_d=dev(t["rho"]), w_d=dev(t["w"]),
                         u_d=dev(t["u"]).reshape(-1)))
-    say("trees:", [(t["L"], t["kind"]) for t in out])
+    say("trees:", [(t["n_leaf"], t["kind"]) for t in out])
     return out
 
 
@@ -76,23 +76,25 @@ def test_batch_equals_single_calls(trees, n_streams):
 
 
 def test_batch_tree_matches_oracle(trees):
-    i = next(k for k, t in enumerate(trees) if t["L"] == 2)
+    """The smallest tree of the batch against the adaptive oracle: the forward
+    on every leaf cell, the adjoint through the dot-product identity."""
+    i = min(range(len(trees)), key=lambda k: trees[k]["n_leaf"])
     t = trees[i]
-    say("tree", i, "vs the oracle")
+    say("tree", i, "with", t["n_leaf"], "leaves vs the oracle")
     b = fmm.Batch([x["plan"] for x in trees], n_streams=4)
     phis, gs, drhos = empty_like_fields(trees)
     b.forward_into([x["rho_d"] for x in trees], phis, gs)
     b.adjoint_into([x["w_d"] for x in trees], [x["u_d"] for x in trees], drhos)
     torch.cuda.synchronize()
-    lay = t["lay"]
-    phi = lay.layout_to_dense(phis[i].cpu().numpy())
-    g = lay.layout_to_dense(gs[i].cpu().numpy().reshape(3, -1))
-    dr = lay.layout_to_dense(drhos[i].cpu().numpy())
-    po, go = O.fmm(t["rho"])
-    do = O.fmm_adjoint(t["w"], t["u"])
-    e = (normwise(phi, po), normwise_vec(g, go), normwise(dr, do))
-    say(f"phi {e[0]:.2e} g {e[1]:.2e} drho {e[2]:.2e}")
-    assert max(e) < 1e-12
+    phi = phis[i].cpu().numpy()
+    g = gs[i].cpu().numpy().reshape(3, -1)
+    dr = drhos[i].cpu().numpy()
+    po, go = O.amr_fmm_sinks(t["lay"], t["rho"])
+    e = (normwise(phi, po), normwise_vec(g, go))
+    lhs = np.sum(t["w"] * po) + np.sum(t["u"] * go)
+    ed = abs(lhs - np.sum(t["rho"] * dr)) / (np.abs(t["w"] * po).sum() + np.abs(t["u"] * go).sum())
+    say(f"phi {e[0]:.2e} g {e[1]:.2e} adjoint identity {ed:.2e}")
+    assert max(e) < 1e-12 and ed < 1e-12
     b.close()
 
 
