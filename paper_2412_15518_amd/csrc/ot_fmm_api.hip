@@ -302,9 +302,10 @@ void cf_table_down(int r2i, double h, double G, std::vector<double> &K)
 }
 
 // Block shape of an adaptive tree's level l (np = 4 << l parents per axis,
-// the grid of its M2L and of its leaf pass): one sub-grid per block from 64
-// parents per axis on (levels 4 and deeper, sparse), rows below
-Block amr_block(int l) { return block_shape(4 << l, (4 << l) >= 64); }
+// the grid of its M2L and of its leaf pass): one sub-grid per block from 16
+// parents per axis on (levels 2 and deeper), so that a block's sinks are all
+// leaves or all refined cells of one sub-grid; rows at levels 0 and 1
+Block amr_block(int l) { return block_shape(4 << l, (4 << l) >= 16); }
 
 // Blocks (64 parents of shape bs) of level l that hold a parent of a listed
 // sub-grid's cells
@@ -335,7 +336,7 @@ void build_amr_tables(ot_fmm_plan P)
         if (P->lnodes[l].empty()) continue;
         P->lblk[l] = blocks_of(l, P->lnodes[l], amr_block(l));
         const double hl = P->h * (double)(1 << (L - l)), r = P->h / hl;
-        leaf_tables(P->Ktab, P->plist_near, r, r * r, r2i, l < L, P->Kst_l[l], P->Ksa_l[l]);
+        leaf_tables(P->Ktab, P->plist_near, r, r * r, r2i, false, P->Kst_l[l], P->Ksa_l[l]);
         P->Kup_l[l].clear();
         P->Kdn_l[l].clear();
         if (!P->lnodes[l - 1].empty()) cf_table(P->plist_near, hl, P->G, -1, P->Kup_l[l]);
@@ -437,13 +438,19 @@ bool unit_has_sources(int np, int blk, char4 P, Block bs)
 // level); runs are balanced in those units and skip the others.  Records
 // per level the list of computed units and how many partial sums a block can
 // receive.
-void build_m2l_schedule(ot_fmm_plan P, int G)
+struct M2LSched {
+    std::vector<M2LDesc> mdesc;
+    std::vector<int32_t> ulist[MAX_LEVELS];
+    int maxp[MAX_LEVELS] = {};
+};
+
+void build_m2l_schedule(ot_fmm_plan P, int G, const std::vector<int32_t> *live_nodes, M2LSched &S)
 {
-    P->mdesc.clear();
+    S.mdesc.clear();
     const int L = P->L;
     for (int l = 0; l < MAX_LEVELS; ++l) {
-        P->dp.lev[l].maxp = 0;
-        P->ulist[l].clear();
+        S.maxp[l] = 0;
+        S.ulist[l].clear();
     }
     if (L < 1) return;
     std::vector<std::vector<int64_t>> pos(L);     // each level's computed units, in order
@@ -454,13 +461,11 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
         const std::vector<char4> &pl = (l == 0) ? P->plist_cube : P->plist_near;
         const int nP = (int)pl.size();
         U[l] = (int64_t)np * np * np / 64 * nP;
-        // adaptive trees: only blocks that hold cells of existing sub-grids
+        // adaptive trees: only blocks that hold cells of the listed sub-grids
         std::vector<char> live;
-        if (P->amr) {
-            std::vector<int32_t> all(P->lnodes[l]);
-            all.insert(all.end(), P->rnodes[l].begin(), P->rnodes[l].end());
+        if (live_nodes) {
             live.assign((size_t)(U[l] / nP), 0);
-            for (int32_t b : blocks_of(l, all, amr_block(l))) live[(size_t)b] = 1;
+            for (int32_t b : blocks_of(l, live_nodes[l], amr_block(l))) live[(size_t)b] = 1;
         }
         const Block bs = P->amr ? amr_block(l) : block_shape(np);
         for (int64_t u = 0; u < U[l]; ++u)
@@ -499,15 +504,15 @@ void build_m2l_schedule(ot_fmm_plan P, int G)
             d.vbeg = (int)((int64_t)r * V[l] / g);
             const int64_t first = (int64_t)(d.ubeg / nP) * nP;
             d.piece0 = (d.ubeg == first) ? 0 : r - run_of(first);
-            P->mdesc.push_back(d);
+            S.mdesc.push_back(d);
         }
-        P->ulist[l].resize(pos[l].size());         // block << 9 | parent offset (nP <= 343)
+        S.ulist[l].resize(pos[l].size());          // block << 9 | parent offset (nP <= 343)
         for (size_t k = 0; k < pos[l].size(); ++k)
-            P->ulist[l][k] = (int32_t)(((pos[l][k] / nP) << 9) | (pos[l][k] % nP));
+            S.ulist[l][k] = (int32_t)(((pos[l][k] / nP) << 9) | (pos[l][k] % nP));
         int maxp = 0;
         for (int64_t blk = 0; blk < U[l] / nP; ++blk)
             maxp = std::max(maxp, run_of(blk * nP + nP - 1) - run_of(blk * nP) + 1);
-        P->dp.lev[l].maxp = maxp;
+        S.maxp[l] = maxp;
     }
 }
 
@@ -555,7 +560,7 @@ void fill_info_amr(ot_fmm_plan P)
                             }
                             if (l > 0 && !near((bx >> 1) - (x >> 1), (by >> 1) - (y >> 1), (bz >> 1) - (z >> 1)))
                                 continue;
-                            if (l == L) ++cnt_p2p;      // finest level: the leaf pass sums them directly
+                            if (leaf && t == 1) ++cnt_p2p;      // two leaves: the leaf pass sums them directly
                             else ++cnt_m2l;
                         }
                 // a leaf's coarse-fine pairs with the leaves near its parent
@@ -753,11 +758,66 @@ int chunk_rule(int64_t nblk)
 
 // Adaptive trees: node kinds and lists on the device, and one view of the
 // plan per level that holds leaves (its leaf pass and coarse-fine pass)
-int setup_amr_views(ot_fmm_plan P)
+int setup_amr_views(ot_fmm_plan P, int G)
 {
     DevPlan &d = P->dp;
     const int L = P->L;
     int rc;
+    // The leaf-sink M2L: for the leaf sub-grids next to a refined one of their
+    // level (the far stencil reaches at most 5 cells, inside the 26
+    // neighbours), the M2L from the refined cells alone; a leaf's far pairs
+    // with leaves are P2P pairs of its leaf pass.
+    std::vector<int32_t> iface[MAX_LEVELS];
+    for (int l = 1; l < L; ++l) {
+        const int m = 1 << l;
+        for (int32_t pk : P->lnodes[l]) {
+            const int x = pk & 1023, y = (pk >> 10) & 1023, z = (pk >> 20) & 1023;
+            bool any = false;
+            for (int e = 0; e < 27 && !any; ++e) {
+                const int qx = x + e % 3 - 1, qy = y + (e / 3) % 3 - 1, qz = z + e / 9 - 1;
+                if (qx < 0 || qy < 0 || qz < 0 || qx >= m || qy >= m || qz >= m) continue;
+                any = P->ntype[l][((size_t)qz * m + qy) * m + qx] == 2;
+            }
+            if (any) iface[l].push_back(pk);
+        }
+    }
+    M2LSched S;
+    build_m2l_schedule(P, G, iface, S);
+    int64_t nunits = 0;
+    for (int l = 0; l < L; ++l) nunits += (int64_t)S.ulist[l].size();
+    P->has_m2l_leaf = nunits > 0;
+    double *cpB[MAX_LEVELS] = {};
+    for (int l = 0; l < L; ++l) {
+        DevLevel &v = d.lev[l];
+        const size_t pp3 = (size_t)v.pp * v.pp * v.pp, np3 = (size_t)v.np * v.np * v.np;
+        v.Mr_ref = nullptr;
+        v.M32_ref = nullptr;
+        if (!P->has_m2l_leaf || P->rnodes[l].empty()) continue;
+        if (d.m2l_fp32) {
+            if ((rc = dev_alloc(P, &v.M32_ref, (size_t)NR * 8 * pp3, true))) return rc;
+        } else if ((rc = dev_alloc(P, &v.Mr_ref, (size_t)NR * 8 * pp3, true))) {
+            return rc;
+        }
+        if (!S.ulist[l].empty() && (rc = dev_alloc(P, &cpB[l], (size_t)std::max(S.maxp[l], 1) * NC * 8 * np3, true)))
+            return rc;
+    }
+    if (P->has_m2l_leaf) {
+        DevPlan &b = P->m2l_leaf;
+        b = d;
+        for (int l = 0; l < L; ++l) {
+            DevLevel &v = b.lev[l];
+            v.Mr = v.Mr_ref;
+            v.M32 = v.M32_ref;
+            v.Cp = cpB[l];
+            v.maxp = S.maxp[l];
+            v.ulist = nullptr;
+            if ((rc = dev_upload(P, &v.ulist, S.ulist[l]))) return rc;
+        }
+        const M2LDesc *md = nullptr;
+        if ((rc = dev_upload(P, &md, S.mdesc))) return rc;
+        b.mdesc = md;
+        b.n_mdesc = (int)S.mdesc.size();
+    }
     for (int l = 0; l <= L; ++l) {
         const uint8_t *nt = nullptr;
         if ((rc = dev_upload(P, &nt, P->ntype[l]))) return rc;
@@ -788,9 +848,10 @@ int setup_amr_views(ot_fmm_plan P)
         const size_t pp3 = (size_t)v.ppL * v.ppL * v.ppL;
         if ((rc = dev_alloc(P, &srcs[l], 4 * 8 * pp3, true))) return rc;
         v.src = srcs[l];
-        v.own_pieces = l < L ? 1 : 0;
+        v.own_Cp = (l < L && cpB[l]) ? cpB[l] : nullptr;
+        v.own_maxp = (l < L) ? S.maxp[l] : 0;
         v.ntype_L = P->dev_ntype[l];
-        v.leaf_subgrid_blocks = (4 << l) >= 64;      // as amr_block(l)
+        v.leaf_subgrid_blocks = (4 << l) >= 16;      // as amr_block(l)
         if ((rc = dev_upload(P, &v.blist, P->lblk[l]))) return rc;
         v.nblist = (int)P->lblk[l].size();
         v.Kcf_up = v.Kcf_dn = nullptr;
@@ -844,7 +905,18 @@ int setup_device(ot_fmm_plan P)
     if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device)) != hipSuccess)
         return hip_fail(e, "hipDeviceGetAttribute");
     if ((e = m2l_blocks_per_cu(d.m2l_fp32, &per_cu)) != hipSuccess) return hip_fail(e, "occupancy of the M2L kernel");
-    build_m2l_schedule(P, std::max(1, ncu * std::max(1, per_cu)));
+    const int G = std::max(1, ncu * std::max(1, per_cu));
+    {
+        // adaptive trees: the M2L of refined sinks (the leaf sinks next to
+        // refined cells get a second, leaf-sink M2L; see setup_amr_views)
+        M2LSched S;
+        build_m2l_schedule(P, G, P->amr ? P->rnodes : nullptr, S);
+        P->mdesc = S.mdesc;
+        for (int l = 0; l < MAX_LEVELS; ++l) {
+            P->ulist[l] = S.ulist[l];
+            d.lev[l].maxp = S.maxp[l];
+        }
+    }
     if ((rc = dev_upload(P, &d.mdesc, P->mdesc))) return rc;
     d.n_plist_near = (int)P->plist_near.size();
     d.n_plist_cube = (int)P->plist_cube.size();
@@ -887,7 +959,7 @@ int setup_device(ot_fmm_plan P)
         // pieces a block never receives stay zero: the schedule is fixed per plan
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }
-    if (P->amr && (rc = setup_amr_views(P))) return rc;
+    if (P->amr && (rc = setup_amr_views(P, G))) return rc;
     // stencil chunks of the leaf passes: the smallest power of two that gives
     // a launch at least 16384 waves (four rounds of the 4096 wave slots the
     // leaf kernels' registers leave), at most LEAF_MAX_CHUNKS per block.  The
@@ -995,8 +1067,10 @@ int amr_run(ot_fmm_plan P, int adj, const double *a0, const double *a1, double *
         ph.end();
     }
     {
-        Phase ph(P, s, OT_FMM_PHASE_M2L, 1);
+        Phase ph(P, s, OT_FMM_PHASE_M2L, 1 + P->has_m2l_leaf);
         if ((e = launch_m2l(d, s)) != hipSuccess) return hip_fail(e, "launch m2l");
+        if (P->has_m2l_leaf && (e = launch_m2l(P->m2l_leaf, s)) != hipSuccess)
+            return hip_fail(e, "launch of the leaf-sink m2l");
         ph.end();
     }
     if (d.n_span > 0) {
@@ -1007,7 +1081,8 @@ int amr_run(ot_fmm_plan P, int adj, const double *a0, const double *a1, double *
     }
     {
         int nl = 0;
-        for (int l = 1; l <= L; ++l) nl += P->lnodes[l].empty() ? 0 : 1 + (l < L || P->view[l].src_up != nullptr);
+        for (int l = 1; l <= L; ++l)
+            nl += P->lnodes[l].empty() ? 0 : 1 + (P->view[l].own_Cp || P->view[l].src_up || P->view[l].src_dn);
         Phase ph(P, s, adj ? OT_FMM_PHASE_LEAF_ADJ : OT_FMM_PHASE_LEAF, nl);
         for (int l = 1; l <= L; ++l) {
             if (P->lnodes[l].empty()) continue;

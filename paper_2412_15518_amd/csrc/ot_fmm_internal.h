@@ -79,6 +79,8 @@ struct DevLevel {
     float *M32;      // [NR/4][8][pp^3][4] the same in FP32 (FP32 M2L; else null)
     double *C;       // [NC][8][np^3] local coefficients (final); null at level L-1
     double *Cp;      // [maxp][NC][8][np^3] M2L partial sums
+    double *Mr_ref;          // adaptive trees: the reduced moments of refined cells alone (leaf cells zero),
+    float *M32_ref;          //   the sources of the leaf-sink M2L (FP64 or FP32 M2L); else null
     const int32_t *ulist;    // the M2L units computed (a source in the domain and, in an adaptive tree,
                              //   a sink in an existing sub-grid), ascending, as block << 9 | offset
     const uint8_t *ntype;    // adaptive trees: per sub-grid of the level, 0 none, 1 leaf, 2 refined (else null)
@@ -131,7 +133,7 @@ struct DevPlan {
     // this struct per level that holds leaves (a "view": L is that level and
     // the leaf fields above describe its leaves); the level arrays lev[] are
     // shared.  Uniform trees leave all of these null / 0.
-    int own_pieces;              // leaf cells of this level are M2L sinks too (levels below the finest)
+    const double *own_Cp; int own_maxp;  // the leaf-sink M2L's pieces of this level (null if none)
     const int32_t *blist; int nblist;   // blocks of the leaf pass holding a leaf sub-grid of this level
     const uint8_t *ntype_L;             // kinds of this level's sub-grids (0 none, 1 leaf, 2 refined)
     int leaf_subgrid_blocks;            // blocks of the leaf pass are sub-grids (block_shape)
@@ -181,6 +183,10 @@ struct ot_fmm_plan_s {
     std::vector<double> Kst_l[otfmm::MAX_LEVELS], Ksa_l[otfmm::MAX_LEVELS];
     std::vector<double> Kup_l[otfmm::MAX_LEVELS], Kdn_l[otfmm::MAX_LEVELS];
     otfmm::DevPlan view[otfmm::MAX_LEVELS];            // per level holding leaves
+    // the leaf-sink M2L of an adaptive tree: a copy of the plan whose levels
+    // read Mr_ref, with its own units, runs and pieces
+    otfmm::DevPlan m2l_leaf{};
+    bool has_m2l_leaf = false;
     const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
     const uint8_t *dev_ntype[otfmm::MAX_LEVELS] = {};
     std::vector<int32_t> ulist[otfmm::MAX_LEVELS];    // M2L units computed, per level

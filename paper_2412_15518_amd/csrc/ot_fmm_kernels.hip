@@ -366,7 +366,8 @@ __device__ __forceinline__ void leaf_p2m(const DevPlan &p, const double *__restr
 // store the moments of cell c of level l (kept under its parent c >> 1):
 // always the reduced form the M2L reads (FP64, or FP32 for the FP32 M2L),
 // and the full moments when an M2M launch reads this level back (full)
-__device__ __forceinline__ void store_moments(const DevLevel &D, int cx, int cy, int cz, const double *Mq, bool full)
+__device__ __forceinline__ void store_moments(const DevLevel &D, int cx, int cy, int cz, const double *Mq, bool full,
+                                              bool refined = false)
 {
     const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
     const int64_t pp = D.pp, pp3 = pp * pp * pp;
@@ -380,6 +381,10 @@ __device__ __forceinline__ void store_moments(const DevLevel &D, int cx, int cy,
         store_reduced(reinterpret_cast<float4 *>(D.M32) + at, cs, Mq, std::make_integer_sequence<int, NR / 4>{});
     else
         store_reduced(reinterpret_cast<double2 *>(D.Mr) + at, cs, Mq, std::make_integer_sequence<int, NR / 2>{});
+    if (refined && D.Mr_ref)        // adaptive trees: the moments of refined cells alone
+        store_reduced(reinterpret_cast<double2 *>(D.Mr_ref) + at, cs, Mq, std::make_integer_sequence<int, NR / 2>{});
+    if (refined && D.M32_ref)
+        store_reduced(reinterpret_cast<float4 *>(D.M32_ref) + at, cs, Mq, std::make_integer_sequence<int, NR / 4>{});
 }
 
 // P2M + M2M into level L-1 when no level lies between it and the root
@@ -1366,7 +1371,7 @@ __global__ __launch_bounds__(WG) void k_amr_m2m(const DevPlan p, int l, const in
             m2m_apply(Mq, e, Mc);
         }
     }
-    store_moments(p.lev[l], x, y, z, Mq, p.lev[l].M != nullptr);
+    store_moments(p.lev[l], x, y, z, Mq, p.lev[l].M != nullptr, true);
 }
 
 // source plane value of cell (x, y, z) of a level whose planes are padded by
@@ -1381,8 +1386,9 @@ __device__ __forceinline__ int64_t src_index(int x, int y, int z, int hp, int pp
 
 // What the leaf pass of an adaptive tree's level p.L leaves out (p: that
 // level's view), added to the outputs it wrote.  Lane = one parent Q of the
-// block, its 8 children the sinks.  Below the finest level: the cell's own
-// M2L expansion at its centre (potential, minus the gradient).  Coarse-fine
+// block, its 8 children the sinks.  Next to refined cells of its level: the
+// cell's own M2L expansion from those refined cells, at its centre (potential,
+// minus the gradient).  Coarse-fine
 // P2P, up: the leaves of level L-1 near Q; down: the children (leaves of
 // level L+1) of the refined cells near each child.
 // A block's CF_WAVES waves split the loops (wave 0 also the own pieces) and
@@ -1410,14 +1416,13 @@ __global__ __launch_bounds__(CF_WAVES * 64) void k_amr_cf(const DevPlan p, doubl
     for (int b = 0; b < 8; ++b)
 #pragma unroll
         for (int a = 0; a < NA; ++a) acc[b][a] = 0.0;
-    if (live && wave == 0 && p.own_pieces) {
-        const DevLevel &D = p.lev[p.L];
-        const int64_t nq = D.np, nq3 = nq * nq * nq;
+    if (live && wave == 0 && p.own_Cp) {
+        const int64_t nq = p.lev[p.L].np, nq3 = nq * nq * nq;
         const int64_t q = ((int64_t)Qz * nq + Qy) * nq + Qx;
-        for (int piece = 0; piece < D.maxp; ++piece) {
+        for (int piece = 0; piece < p.own_maxp; ++piece) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                const double *cp = D.Cp + ((int64_t)piece * NC * 8 + b) * nq3 + q;
+                const double *cp = p.own_Cp + ((int64_t)piece * NC * 8 + b) * nq3 + q;
                 acc[b][0] += cp[0];
                 if constexpr (!ADJ) {
                     acc[b][1 % NA] -= cp[1 * 8 * nq3];
@@ -1684,7 +1689,7 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 
 hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, hipStream_t s)
 {
-    if (v.nblist <= 0 || (!v.own_pieces && !v.src_up && !v.src_dn)) return hipSuccess;
+    if (v.nblist <= 0 || (!v.own_Cp && !v.src_up && !v.src_dn)) return hipSuccess;
     if (adj)
         hipLaunchKernelGGL(k_amr_cf<true>, dim3(v.nblist), dim3(CF_WAVES * 64), 0, s, v, out0, out1);
     else
