@@ -822,7 +822,6 @@ int setup_amr_views(ot_fmm_plan P, int G)
         const uint8_t *nt = nullptr;
         if ((rc = dev_upload(P, &nt, P->ntype[l]))) return rc;
         P->dev_ntype[l] = nt;
-        if (l < L) d.lev[l].ntype = nt;
         if ((rc = dev_upload(P, &P->dev_lnodes[l], P->lnodes[l]))) return rc;
         if ((rc = dev_upload(P, &P->dev_rnodes[l], P->rnodes[l]))) return rc;
     }
@@ -1073,10 +1072,13 @@ int amr_run(ot_fmm_plan P, int adj, const double *a0, const double *a1, double *
             return hip_fail(e, "launch of the leaf-sink m2l");
         ph.end();
     }
-    if (d.n_span > 0) {
-        Phase ph(P, s, OT_FMM_PHASE_L2L, d.n_span);
-        for (int i = 0; i < d.n_span; ++i)
-            if ((e = launch_l2l_span(d, i, s)) != hipSuccess) return hip_fail(e, "launch l2l");
+    if (L >= 2) {
+        // level by level over the refined sub-grids (a leaf cell's final
+        // local has no reader); levels 0 .. L-2, the leaf passes form L-1
+        Phase ph(P, s, OT_FMM_PHASE_L2L, L - 1);
+        for (int l = 0; l <= L - 2; ++l)
+            if ((e = launch_amr_l2l(d, l, P->dev_rnodes[l], (int)P->rnodes[l].size(), s)) != hipSuccess)
+                return hip_fail(e, "launch of an L2L level");
         ph.end();
     }
     {

@@ -83,7 +83,6 @@ struct DevLevel {
     float *M32_ref;          //   the sources of the leaf-sink M2L (FP64 or FP32 M2L); else null
     const int32_t *ulist;    // the M2L units computed (a source in the domain and, in an adaptive tree,
                              //   a sink in an existing sub-grid), ascending, as block << 9 | offset
-    const uint8_t *ntype;    // adaptive trees: per sub-grid of the level, 0 none, 1 leaf, 2 refined (else null)
 };
 
 // M2L work: a block = 64 sink parents of one level (bx*by*bz parents, lane =
@@ -222,6 +221,8 @@ hipError_t launch_amr_leaf_moments(const DevPlan &v, int adj, const int32_t *nod
 //   any plan whose lev[] is the tree's when level l + 1 holds no leaves)
 hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes, int n, const uint8_t *child_type,
                           const double *a0, const double *a1, hipStream_t s);
+//   final local expansions of the n refined sub-grids of level l (p: the plan)
+hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s);
 //   for the leaves of level v.L: their own level's M2L part (below the finest
 //   level) and their P2P pairs with leaves one level up or down
 hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, hipStream_t s);

@@ -920,17 +920,11 @@ __global__ __launch_bounds__(L2L_SPAN_WG) void k_l2l_span(const DevPlan p, int l
     const int t = threadIdx.x;
     const int j = (t == 0) ? 0 : (t < 9 ? 1 : 2);
     const int ci = (t == 0) ? 0 : (t < 9 ? t - 1 : t - 9);
-    bool act = t < 73 && j < nlev;
+    const bool act = t < 73 && j < nlev;
     const int lv = ltop + j;
     int cx, cy, cz;
     span_cell(ax, ay, az, j, ci, cx, cy, cz);
-    if (act && p.lev[lv].ntype) {
-        // adaptive tree: only cells of refined sub-grids.  A leaf cell's final
-        // expansion has no reader: it has no children, and the leaf passes
-        // form their locals from the parent level and the cell's own pieces.
-        const int64_t m = (int64_t)1 << lv;
-        act = p.lev[lv].ntype[((int64_t)(cz >> 3) * m + (cy >> 3)) * m + (cx >> 3)] == 2;
-    }
+
     const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
     double C[NC];
 #pragma unroll
@@ -1374,6 +1368,40 @@ __global__ __launch_bounds__(WG) void k_amr_m2m(const DevPlan p, int l, const in
     store_moments(p.lev[l], x, y, z, Mq, p.lev[l].M != nullptr, true);
 }
 
+// final local expansions of the cells of the n refined sub-grids of level l:
+// their M2L pieces plus the shift of the parent's (the same sums, in the same
+// order, as k_l2l_span)
+__global__ __launch_bounds__(WG) void k_amr_l2l(const DevPlan p, int l, const int32_t *__restrict__ nodes, int n)
+{
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * 512) return;
+    int cx, cy, cz;
+    amr_cell(nodes[t >> 9], (int)(t & 511), cx, cy, cz);
+    const DevLevel &D = p.lev[l];
+    const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+    const int64_t np = D.np, np3 = np * np * np;
+    const int64_t q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
+    double C[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) C[k] = 0.0;
+    add_pieces<4>(C, D.Cp + bs * np3 + q, 8 * np3, D.maxp);
+    if (l > 0) {
+        const DevLevel &Dp = p.lev[l - 1];
+        const int Rx = cx >> 1, Ry = cy >> 1, Rz = cz >> 1;
+        const int bR = (Rx & 1) + 2 * (Ry & 1) + 4 * (Rz & 1);
+        const int64_t npp = Dp.np, npp3 = npp * npp * npp;
+        const int64_t qR = ((int64_t)(Rz >> 1) * npp + (Ry >> 1)) * npp + (Rx >> 1);
+        double Cp[NC], e[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Cp[k] = Dp.C[(k * 8 + bR) * npp3 + qR];
+        const double hh = 0.5 * D.h;
+        taylor((cx & 1) ? hh : -hh, (cy & 1) ? hh : -hh, (cz & 1) ? hh : -hh, e);   // e(z_c - z_parent)
+        l2l_apply(C, e, Cp);
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) D.C[(k * 8 + bs) * np3 + q] = C[k];
+}
+
 // source plane value of cell (x, y, z) of a level whose planes are padded by
 // hp parents (pp per axis): plane j, cell stored under its parent
 __device__ __forceinline__ int64_t src_index(int x, int y, int z, int hp, int pp, int j)
@@ -1684,6 +1712,13 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
         hipLaunchKernelGGL(k_amr_m2m<true>, grid, dim3(WG), 0, s, v, l, nodes, n, child_type, a0, a1);
     else
         hipLaunchKernelGGL(k_amr_m2m<false>, grid, dim3(WG), 0, s, v, l, nodes, n, child_type, a0, a1);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_amr_l2l, dim3(grid_for((int64_t)n * 512)), dim3(WG), 0, s, p, l, nodes, n);
     return hipGetLastError();
 }
 
