@@ -334,7 +334,15 @@ void build_amr_tables(ot_fmm_plan P)
     for (int l = 1; l <= L; ++l) {
         P->lblk[l].clear();
         if (P->lnodes[l].empty()) continue;
-        P->lblk[l] = blocks_of(l, P->lnodes[l], amr_block(l));
+        // the leaf pass's blocks (64 parents each): rows where at least 3/4 of
+        // the rows' parents lie in leaf sub-grids of this level (rows load
+        // contiguously), else one sub-grid per block
+        P->lsub[l] = 0;
+        P->lblk[l] = blocks_of(l, P->lnodes[l], block_shape(4 << l));
+        if ((int64_t)P->lnodes[l].size() * 4 < (int64_t)P->lblk[l].size() * 3) {
+            P->lsub[l] = 1;
+            P->lblk[l] = blocks_of(l, P->lnodes[l], block_shape(4 << l, 1));
+        }
         const double hl = P->h * (double)(1 << (L - l)), r = P->h / hl;
         leaf_tables(P->Ktab, P->plist_near, r, r * r, r2i, false, P->Kst_l[l], P->Ksa_l[l]);
         P->Kup_l[l].clear();
@@ -850,7 +858,7 @@ int setup_amr_views(ot_fmm_plan P, int G)
         v.own_Cp = (l < L && cpB[l]) ? cpB[l] : nullptr;
         v.own_maxp = (l < L) ? S.maxp[l] : 0;
         v.ntype_L = P->dev_ntype[l];
-        v.leaf_subgrid_blocks = (4 << l) >= 16;      // as amr_block(l)
+        v.leaf_subgrid_blocks = P->lsub[l];
         if ((rc = dev_upload(P, &v.blist, P->lblk[l]))) return rc;
         v.nblist = (int)P->lblk[l].size();
         v.Kcf_up = v.Kcf_dn = nullptr;

@@ -179,6 +179,7 @@ struct ot_fmm_plan_s {
     std::vector<int32_t> lnodes[otfmm::MAX_LEVELS];    // leaf sub-grids per level, packed x | y << 10 | z << 20
     std::vector<int32_t> rnodes[otfmm::MAX_LEVELS];    // refined sub-grids per level, packed alike
     std::vector<int32_t> lblk[otfmm::MAX_LEVELS];      // leaf-pass blocks per level
+    int lsub[otfmm::MAX_LEVELS] = {};                  // 1: those blocks are sub-grids, 0: rows
     std::vector<double> Kst_l[otfmm::MAX_LEVELS], Ksa_l[otfmm::MAX_LEVELS];
     std::vector<double> Kup_l[otfmm::MAX_LEVELS], Kdn_l[otfmm::MAX_LEVELS];
     otfmm::DevPlan view[otfmm::MAX_LEVELS];            // per level holding leaves
