@@ -127,7 +127,8 @@ typedef struct {
     double  bytes_forward;         /* algorithmic HBM bytes per forward */
     double  bytes_adjoint;
     size_t  device_bytes;          /* device memory owned by the plan */
-    int32_t leaf_chunks_forward;   /* stencil chunks (waves per leaf block) of the forward leaf pass */
+    int32_t leaf_chunks_forward;   /* stencil chunks (waves per leaf block) of the forward leaf pass
+                                      (adaptive trees: of the deepest level's) */
     int32_t leaf_chunks_adjoint;   /* the same for the adjoint */
 } ot_fmm_info;
 
@@ -139,8 +140,9 @@ typedef struct {
  * level or not within the parent, duplicate nodes, an internal node without
  * all 8 children, a leaf with children.  UNSUPPORTED_LAYOUT: deeper than 6
  * levels, or an adaptive tree whose refined sub-grids miss a same-level
- * neighbour (touching leaves more than one level apart).  Adaptive trees
- * ignore OT_FMM_AUTOTUNE (the size rule picks each level's chunk count). */
+ * neighbour (touching leaves more than one level apart).  In adaptive trees
+ * every level holding leaves has its own leaf pass, whose chunk count the size
+ * rule (or OT_FMM_AUTOTUNE, per level) picks. */
 int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order,
                        uint32_t flags, ot_fmm_plan *out);
 

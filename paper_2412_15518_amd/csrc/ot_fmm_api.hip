@@ -713,12 +713,12 @@ void free_device(ot_fmm_plan P)
     P->timing.pool.clear();
 }
 
-// Time each leaf pass with 1, 2, 4 and 8 stencil chunks (a warm-up launch,
-// then the best of three single launches, on the plan's zeroed scratch and
-// temporary outputs) and keep the fastest count.
-int autotune_leaf(ot_fmm_plan P)
+// Time each leaf pass of d (the plan, or one level's view of an adaptive
+// tree) with 1, 2, 4 and 8 stencil chunks (a warm-up launch, then the best of
+// three single launches, on the plan's zeroed scratch and temporary outputs)
+// and keep the fastest count.
+int autotune_leaf(ot_fmm_plan P, DevPlan &d)
 {
-    DevPlan &d = P->dp;
     const size_t N = (size_t)d.n_leaf_cells;
     double *o0 = nullptr, *o1 = nullptr;
     hipStream_t st = nullptr;
@@ -975,7 +975,14 @@ int setup_device(ot_fmm_plan P)
     d.leaf_chunks[0] = d.leaf_chunks[1] = chunk_rule((int64_t)d.npL * d.npL * d.npL / 64);
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize after plan setup");
-    if ((P->flags & OT_FMM_AUTOTUNE) && !P->amr && (rc = autotune_leaf(P))) return rc;
+    if (P->flags & OT_FMM_AUTOTUNE) {
+        if (!P->amr) {
+            if ((rc = autotune_leaf(P, d))) return rc;
+        } else {
+            for (int l = 1; l <= L; ++l)
+                if (!P->lnodes[l].empty() && (rc = autotune_leaf(P, P->view[l]))) return rc;
+        }
+    }
     P->has_device = true;
     return OT_FMM_OK;
 }
@@ -1289,8 +1296,9 @@ int ot_fmm_plan_info(ot_fmm_plan P, ot_fmm_info *info)
 {
     if (!P || !info) return fail(OT_FMM_INVALID_ARGUMENT, "plan or info is NULL");
     *info = P->info;
-    info->leaf_chunks_forward = P->has_device ? P->dp.leaf_chunks[0] : 0;
-    info->leaf_chunks_adjoint = P->has_device ? P->dp.leaf_chunks[1] : 0;
+    const DevPlan &lp = P->amr ? P->view[P->L] : P->dp;     // adaptive trees: the deepest level's pass
+    info->leaf_chunks_forward = P->has_device ? lp.leaf_chunks[0] : 0;
+    info->leaf_chunks_adjoint = P->has_device ? lp.leaf_chunks[1] : 0;
     return OT_FMM_OK;
 }
 

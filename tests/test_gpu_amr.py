@@ -114,6 +114,24 @@ def test_repeat_bitwise_and_momentum():
     assert np.abs(F.sum(axis=1)).max() / np.abs(F).sum() < 1e-13
 
 
+def test_autotuned_and_set_chunks_agree():
+    """Per-level chunk counts from the timing tuner, and counts set by hand,
+    change only the rounding."""
+    d = W.small_amr("blob")
+    lay, rho = d["layout"], d["rho"]
+    say("amr autotune")
+    p0 = fmm.Plan(lay)
+    p1 = fmm.Plan(lay, autotune=True)
+    phi0, g0 = forward(p0, rho)
+    phi1, g1 = forward(p1, rho)
+    assert normwise(phi1, phi0) < 1e-14 and normwise_vec(g1, g0) < 1e-14
+    for c in (1, 8):
+        p0.set_leaf_chunks(c, c)
+        phic, gc = forward(p0, rho)
+        assert normwise(phic, phi0) < 1e-14 and normwise_vec(gc, g0) < 1e-14
+        assert p0.info()["leaf_chunks_forward"] == c
+
+
 def test_fp32_m2l_on_adaptive_tree():
     d = W.small_amr("edge")
     lay, rho = d["layout"], d["rho"]

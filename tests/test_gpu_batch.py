@@ -146,9 +146,9 @@ def test_capture_refused_while_timing(trees):
 
 
 def test_batch_mixed_depths_and_precisions():
-    """Depths 0, 1 and 5 (no M2L, one level, two M2M spans) with one FP32-M2L
-    plan: the shared M2L launch takes each precision group apart, and every
-    plan still gives its single call's bits."""
+    """Depths 0, 1 and 5 (no M2L, one level, two M2M spans), one FP32-M2L plan
+    and one adaptive tree in one batch: every plan still gives its single
+    call's bits."""
     rng = np.random.default_rng(900)
     specs = [(0, False), (1, False), (5, False), (2, True), (3, False)]
     plans, rhos, ws, us = [], [], [], []
@@ -160,6 +160,13 @@ def test_batch_mixed_depths_and_precisions():
         rhos.append(dev(rng.uniform(0.0, 1.0, (n, n, n))))
         ws.append(dev(rng.standard_normal((n, n, n))))
         us.append(dev(rng.standard_normal((3, n, n, n))).reshape(-1))
+    amr = W.small_amr("edge")
+    plans.append(fmm.Plan(amr["layout"]))
+    na = amr["layout"].n_leaf_cells
+    rhos.append(torch.from_numpy(amr["rho"]).cuda())
+    ws.append(torch.from_numpy(rng.standard_normal(na)).cuda())
+    us.append(torch.from_numpy(rng.standard_normal(3 * na)).cuda())
+    specs = specs + [("adaptive", False)]
     say("mixed batch:", specs)
     ref = []
     for p, r, w, u in zip(plans, rhos, ws, us):
