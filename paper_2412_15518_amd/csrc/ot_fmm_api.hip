@@ -452,7 +452,28 @@ struct M2LSched {
     int maxp[MAX_LEVELS] = {};
 };
 
-void build_m2l_schedule(ot_fmm_plan P, int G, const std::vector<int32_t> *live_nodes, M2LSched &S)
+// Whether unit (block blk, parent offset P) of level l reads a cell of a
+// refined sub-grid: the block's parents shifted by P cover sub-grids (parent
+// >> 2) of which one is refined
+bool unit_reads_refined(ot_fmm_plan P_, int l, int blk, char4 P, Block bs)
+{
+    const int np = 4 << l, m = 1 << l;
+    const int nbx = np / bs.bx, nby = np / bs.by;
+    const int x0 = (blk % nbx) * bs.bx + P.x, y0 = ((blk / nbx) % nby) * bs.by + P.y,
+              z0 = (blk / (nbx * nby)) * bs.bz + P.z;
+    auto lo = [](int a) { return std::max(a, 0) >> 2; };
+    auto hi = [np](int a) { return std::min(a, np - 1) >> 2; };
+    for (int z = lo(z0); z <= hi(z0 + bs.bz - 1); ++z)
+        for (int y = lo(y0); y <= hi(y0 + bs.by - 1); ++y)
+            for (int x = lo(x0); x <= hi(x0 + bs.bx - 1); ++x)
+                if (x < m && y < m && z < m && P_->ntype[l][((size_t)z * m + y) * m + x] == 2) return true;
+    return false;
+}
+
+// live_nodes (per level, or null): only blocks holding cells of these sub-grids;
+// refined_sources: only units that read a cell of a refined sub-grid
+void build_m2l_schedule(ot_fmm_plan P, int G, const std::vector<int32_t> *live_nodes, M2LSched &S,
+                        bool refined_sources = false)
 {
     S.mdesc.clear();
     const int L = P->L;
@@ -477,7 +498,8 @@ void build_m2l_schedule(ot_fmm_plan P, int G, const std::vector<int32_t> *live_n
         }
         const Block bs = P->amr ? amr_block(l) : block_shape(np);
         for (int64_t u = 0; u < U[l]; ++u)
-            if (unit_has_sources(np, (int)(u / nP), pl[u % nP], bs) && (live.empty() || live[(size_t)(u / nP)])) {
+            if (unit_has_sources(np, (int)(u / nP), pl[u % nP], bs) && (live.empty() || live[(size_t)(u / nP)]) &&
+                (!refined_sources || unit_reads_refined(P, l, (int)(u / nP), pl[u % nP], bs))) {
                 pos[l].push_back(u);
             }
         V[l] = (int64_t)pos[l].size();
@@ -790,7 +812,7 @@ int setup_amr_views(ot_fmm_plan P, int G)
         }
     }
     M2LSched S;
-    build_m2l_schedule(P, G, iface, S);
+    build_m2l_schedule(P, G, iface, S, true);
     int64_t nunits = 0;
     for (int l = 0; l < L; ++l) nunits += (int64_t)S.ulist[l].size();
     P->has_m2l_leaf = nunits > 0;

@@ -1419,8 +1419,8 @@ __device__ __forceinline__ int64_t src_index(int x, int y, int z, int hp, int pp
 // minus the gradient).  Coarse-fine
 // P2P, up: the leaves of level L-1 near Q; down: the children (leaves of
 // level L+1) of the refined cells near each child.
-// A block's CF_WAVES waves split the loops (wave 0 also the own pieces) and
-// meet in LDS in the fixed order ((w1 + w2) + ...) + w0.
+// A block's CF_WAVES waves split the loops and the pieces and meet in LDS in
+// the fixed order ((w1 + w2) + ...) + w0.
 constexpr int CF_WAVES = 8;
 template <bool ADJ>
 __global__ __launch_bounds__(CF_WAVES * 64) void k_amr_cf(const DevPlan p, double *__restrict__ out0,
@@ -1444,10 +1444,11 @@ __global__ __launch_bounds__(CF_WAVES * 64) void k_amr_cf(const DevPlan p, doubl
     for (int b = 0; b < 8; ++b)
 #pragma unroll
         for (int a = 0; a < NA; ++a) acc[b][a] = 0.0;
-    if (live && wave == 0 && p.own_Cp) {
+    if (live && p.own_Cp) {
+        // the pieces are dealt to the waves (piece k to wave k mod CF_WAVES)
         const int64_t nq = p.lev[p.L].np, nq3 = nq * nq * nq;
         const int64_t q = ((int64_t)Qz * nq + Qy) * nq + Qx;
-        for (int piece = 0; piece < p.own_maxp; ++piece) {
+        for (int piece = wave; piece < p.own_maxp; piece += CF_WAVES) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const double *cp = p.own_Cp + ((int64_t)piece * NC * 8 + b) * nq3 + q;
