@@ -169,7 +169,7 @@ def bench_amr(args):
     import torch
 
     from paper_2412_15518_amd import fmm, workloads as W
-    d = W.cfg3_amr()
+    d = W.adaptive_two_polytropes()
     lay = d["layout"]
     c0 = time.perf_counter()
     plan = fmm.Plan(lay)
@@ -254,7 +254,7 @@ def main():
 
     torch.cuda.set_device(0)
     log("generating the 128^3 two-polytrope workload")
-    cfg = W.cfg2_two_polytropes()
+    cfg = W.two_polytropes()
     lay = W.uniform_layout(cfg["L"])
     plan = fmm.Plan(lay, theta=0.4, order=3)
     info = plan.info()

@@ -200,12 +200,12 @@ def polytrope(n: int, centre, radius: float, rho_c: float, n_index: float = 1.5)
 # --------------------------------------------------------------------------
 # the five workloads
 # --------------------------------------------------------------------------
-def cfg1_sphere():
+def sphere_32():
     """32^3 (L = 2): rho = 1 for centres within 12 of the box centre, else 0."""
     return dict(L=2, rho=uniform_sphere(32, 12.0, (16.0, 16.0, 16.0)))
 
 
-def cfg2_two_polytropes(n: int = 128, seed: int = 2, with_cotangents: bool = True):
+def two_polytropes(n: int = 128, seed: int = 2, with_cotangents: bool = True):
     """128^3 (L = 4): two n = 1.5 polytropes (rho_c 1.0, R 20 at x = 39; rho_c 0.6,
     R 14 at x = 89; y = z = 64), a 1e-10 floor, and x(1 + 0.01 U(-1,1)) noise.
     The cotangents w, u ~ N(0,1) for the forward+adjoint pass follow from the
@@ -224,7 +224,7 @@ def cfg2_two_polytropes(n: int = 128, seed: int = 2, with_cotangents: bool = Tru
     return out
 
 
-def cfg5_lognormal(n: int = 64, seed: int = 5, n_fd: int = 64):
+def lognormal_sphere(n: int = 64, seed: int = 5, n_fd: int = 64):
     """64^3 (L = 3): rho = exp(0.5 z) * [r <= 24] about the box centre with
     z ~ N(0,1); cotangents w, u ~ N(0,1); n_fd distinct finite-difference
     cells.  Drawn in the fixed order rho, w, u, cells."""
@@ -418,7 +418,7 @@ def _polytrope_at(points: np.ndarray, centre, radius: float, rho_c: float, n_ind
     return np.where(inside, rho_c * np.maximum(theta, 0.0) ** n_index, 0.0)
 
 
-def cfg3_amr(seed: int = 3, base: int = 3, extra: int = 3, thresh: float = 1e-3,
+def adaptive_two_polytropes(seed: int = 3, base: int = 3, extra: int = 3, thresh: float = 1e-3,
              with_cotangents: bool = True):
     """Adaptive octree over a box of (8 * 2^(base + extra))^3 finest cells
     (h = 1): uniform down to level `base`, then refined `extra` more levels

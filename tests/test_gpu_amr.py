@@ -146,7 +146,7 @@ def test_workload_tree_sampled():
     """The adaptive workload (1296 leaf sub-grids on levels 3..6 of a 512^3
     box): sampled sinks on every leaf level against the oracle, and the
     adjoint against the GPU forward over the whole tree."""
-    d = W.cfg3_amr()
+    d = W.adaptive_two_polytropes()
     lay, rho = d["layout"], d["rho"]
     say("amr workload plan", lay.n_nodes, "nodes", lay.n_leaf_cells, "cells")
     plan = fmm.Plan(lay)

@@ -70,7 +70,7 @@ def test_every_chunk_count_matches_oracle(L):
 
 
 def test_autotuned_plan_is_valid_and_repeats():
-    cfg = W.cfg5_lognormal()
+    cfg = W.lognormal_sphere()
     lay = W.uniform_layout(cfg["L"])
     plan = fmm.Plan(lay, autotune=True)
     inf = plan.info()

@@ -93,7 +93,7 @@ def test_fp32_against_fp64_path_full_size():
     """128^3 two-polytrope workload: forward and adjoint of the FP32 path
     against the FP64 path on the whole grid, and the forward against the
     oracle on sampled sinks."""
-    cfg = W.cfg2_two_polytropes()
+    cfg = W.two_polytropes()
     lay = W.uniform_layout(cfg["L"])
     say("128^3 fp32 and fp64")
     a = run(lay, rho=cfg["rho"], w=cfg["w"], u=cfg["u"], fp32=True)
@@ -112,7 +112,7 @@ def test_fp32_against_fp64_path_full_size():
 
 
 def test_fp32_deterministic_bitwise():
-    cfg = W.cfg5_lognormal()
+    cfg = W.lognormal_sphere()
     lay = W.uniform_layout(cfg["L"])
     plan = fmm.Plan(lay, m2l_fp32=True)
     r = to_dev(lay, cfg["rho"])

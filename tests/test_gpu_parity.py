@@ -96,10 +96,10 @@ def test_forward_scaled_units():
     assert normwise_vec(g, go) < TOL
 
 
-def test_cfg1_sphere():
+def test_sphere_32():
     """32^3 uniform sphere: GPU == oracle FMM; accuracy against the direct sum
     is the method's (stated, ~1e-4 in phi, ~3e-3 in g)."""
-    cfg = W.cfg1_sphere()
+    cfg = W.sphere_32()
     lay = W.uniform_layout(cfg["L"])
     phi, g = gpu_forward(lay, cfg["rho"])
     po, go = O.fmm(cfg["rho"])
@@ -107,12 +107,12 @@ def test_cfg1_sphere():
     assert normwise_vec(g, go) < TOL
     pd, gd = O.direct(cfg["rho"])
     ep, eg = normwise(phi, pd), normwise_vec(g, gd)
-    say(f"cfg1 vs direct sum: phi {ep:.3e}  g {eg:.3e}")
+    say(f"32^3 sphere vs direct sum: phi {ep:.3e}  g {eg:.3e}")
     assert ep < 2e-4 and eg < 5e-3
 
 
-def test_cfg5_forward():
-    cfg = W.cfg5_lognormal()
+def test_lognormal_sphere_forward():
+    cfg = W.lognormal_sphere()
     lay = W.uniform_layout(cfg["L"], order="morton")
     phi, g = gpu_forward(lay, cfg["rho"])
     po, go = O.fmm(cfg["rho"])
@@ -133,10 +133,10 @@ def test_edge_cases_zero_and_point():
     assert normwise_vec(g, go) < TOL
 
 
-def test_cfg2_sampled_full_size():
+def test_two_polytropes_sampled_full_size():
     """128^3 two-polytrope workload, one forward as the benchmark runs it;
     oracle evaluated per sink on 512 sampled cells (plus the domain corners)."""
-    cfg = W.cfg2_two_polytropes(with_cotangents=False)
+    cfg = W.two_polytropes(with_cotangents=False)
     lay = W.uniform_layout(cfg["L"])
     phi, g = gpu_forward(lay, cfg["rho"])
     rng = np.random.default_rng(2024)
@@ -232,7 +232,7 @@ def test_depth6_largest_supported_tree():
 
 
 def test_deterministic_bitwise():
-    cfg = W.cfg5_lognormal()
+    cfg = W.lognormal_sphere()
     lay = W.uniform_layout(cfg["L"])
     plan = fmm.Plan(lay)
     r = to_dev(lay, cfg["rho"])
@@ -270,7 +270,7 @@ def test_adjoint_other_layout_orders(order):
     assert normwise(dr, O.fmm_adjoint(w, u)) < TOL
 
 
-def test_adjoint_cfg5_matches_oracle_and_fd():
+def test_adjoint_lognormal_sphere_matches_oracle_and_fd():
     """64^3 lognormal sphere: GPU adjoint == oracle adjoint, and central finite
     differences of L = sum w phi + sum u g through the GPU forward on the 64
     seeded cells.  F is linear, so the difference quotient has no truncation
@@ -279,7 +279,7 @@ def test_adjoint_cfg5_matches_oracle_and_fd():
     the FD error is about sqrt(2) * 25 eps ||(w phi, u g)||_2 / (2 eps_fd)
     ~ 18 eps S2 / eps_fd.  The bar is 50 eps S2 / eps_fd (for eps_fd = 1e-6
     that is ~2e-4 of max|drho|; measured 3.3e-5)."""
-    cfg = W.cfg5_lognormal()
+    cfg = W.lognormal_sphere()
     lay = W.uniform_layout(cfg["L"])
     plan = fmm.Plan(lay)
     dr = gpu_adjoint(lay, cfg["w"], cfg["u"], plan=plan)
@@ -316,7 +316,7 @@ def test_adjoint_cfg5_matches_oracle_and_fd():
 def test_adjoint_identities_full_size():
     """128^3: dot-product identity and, for u = 0, the adjoint equals the
     forward potential of w (the potential operator is symmetric)."""
-    cfg = W.cfg2_two_polytropes()
+    cfg = W.two_polytropes()
     lay = W.uniform_layout(cfg["L"])
     plan = fmm.Plan(lay)
     rho, w, u = to_dev(lay, cfg["rho"]), to_dev(lay, cfg["w"]), to_dev(lay, cfg["u"])

@@ -51,7 +51,7 @@ def test_pair_cover_exact(kind, nsample):
 
 
 def test_pair_cover_workload_sample():
-    d = W.cfg3_amr(with_cotangents=False)
+    d = W.adaptive_two_polytropes(with_cotangents=False)
     lay = d["layout"]
     rng = np.random.default_rng(12)
     # sinks on every leaf level
@@ -175,7 +175,7 @@ def test_small_trees_balanced(kind):
 def test_workload_tree():
     """The adaptive workload: uniform to level 3, three more levels, balanced;
     the leaf counts land in the stated range of about 600 to 2500 sub-grids."""
-    d = W.cfg3_amr(with_cotangents=False)
+    d = W.adaptive_two_polytropes(with_cotangents=False)
     lay = d["layout"]
     assert lay.depth == 6
     assert np.all(lay.is_leaf[lay.level < 3] == 0)

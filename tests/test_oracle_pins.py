@@ -65,7 +65,7 @@ def test_uniform_sphere_closed_form(which):
     -GM r_hat/r^2 outside, with M the lattice mass and R = (3M/4pi)^(1/3).
     Cells within 2h of the surface are excluded (staircase); the remaining
     difference is the discretisation of the lattice, stated below."""
-    cfg = W.cfg1_sphere()
+    cfg = W.sphere_32()
     rho = cfg["rho"]
     phi, g = O.direct(rho) if which == "direct" else O.fmm(rho)
     M = rho.sum()
@@ -203,7 +203,7 @@ def test_pair_counts_golden():
 
 # ---------------------------------------------------------------- convergence
 def test_convergence_in_order():
-    rho = W.cfg1_sphere()["rho"]
+    rho = W.sphere_32()["rho"]
     pd, gd = O.direct(rho)
     errs = []
     for p in range(0, 6):
@@ -217,7 +217,7 @@ def test_convergence_in_order():
 
 
 def test_convergence_in_theta():
-    rho = W.cfg1_sphere()["rho"]
+    rho = W.sphere_32()["rho"]
     pd, gd = O.direct(rho)
     prev = None
     for theta in (0.9, 0.7, 0.5, 0.4):
