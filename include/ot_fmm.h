@@ -183,6 +183,10 @@ const char *ot_fmm_last_error(void);   /* message of this thread's last failure 
 #define OT_FMM_PHASE_UPWARD_LEAF_ADJ  5   /* P2M of the dual sources + M2M of up to 3 levels, adjoint */
 #define OT_FMM_PHASE_LEAF_ADJ         6
 #define OT_FMM_PHASE_TOTAL            7   /* whole forward or adjoint call */
+/* Adaptive trees: UPWARD_LEAF(_ADJ) holds the whole upward pass (leaf moments
+ * and M2M level by level), M2M is empty, M2L holds its two launches (refined
+ * sinks; leaf sinks next to refined cells), L2L the level-by-level L2L, and
+ * LEAF(_ADJ) every level's leaf pass and coarse-fine pass. */
 #define OT_FMM_NUM_PHASES             8
 
 typedef struct {
