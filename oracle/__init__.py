@@ -50,6 +50,8 @@ def _load():
     lib.oracle_moments.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, _dp]
     lib.oracle_pair_counts.argtypes = [C.c_int, C.c_double, _i64p, _i64p]
     lib.oracle_pair_counts_slab.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _i64p, _i64p]
+    lib.oracle_amcorr_sinks.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _dp,
+                                        C.c_int64, _i64p, _dp]
     _tree = [C.c_int64, _i32p, _i32p, _u8p]
     lib.oracle_amr_sinks.argtypes = _tree + [C.c_int, C.c_double, C.c_double, C.c_double, _dp,
                                              C.c_int64, _i64p, _dp, _dp]
@@ -226,3 +228,17 @@ def amr_cover(layout, sink, theta=0.4):
     mult = np.zeros(int(layout.is_leaf.sum()) * 512, dtype=np.int32)
     _check(_load().oracle_amr_cover(*t, theta, int(sink), mult.ctypes.data_as(_i32p)), "amr_cover")
     return mult
+
+
+def am_correction(rho, p=3, theta=0.4, h=1.0, G=1.0, sinks=None):
+    """Spin torque per unit mass t (3, ...) of the angular-momentum correction:
+    sum_i m_i (x_i x g_i + t_i) = 0 for the FMM's g (uniform trees).  sinks:
+    None for the whole grid (dense (3, n, n, n)), else dense cell indices."""
+    rho = _c64(rho)
+    L = _level_of(rho)
+    n = rho.shape[-1]
+    s = np.arange(n ** 3, dtype=np.int64) if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+    t = np.zeros((3, s.size))
+    _check(_load().oracle_amcorr_sinks(L, p, theta, h, G, _d(rho), s.size, s.ctypes.data_as(_i64p), _d(t)),
+           "amcorr_sinks")
+    return t.reshape(3, n, n, n) if sinks is None else t

@@ -1240,3 +1240,82 @@ int oracle_amr_cover(int64_t nn, const int32_t *lvl, const int32_t *crd, const u
     amr_free(&A);
     return rc;
 }
+
+/* ======================================================================== */
+/* Angular-momentum correction (spin torque per unit mass)                   */
+/* ======================================================================== */
+/*
+ * Sec. 4.3 names an angular-momentum-conserving correction of the FMM without
+ * its formula.  Reading used here.  For one ordered M2L pair (A <- B) with
+ * R = z_A - z_B, the truncated pair energy depends on the fixed expansion
+ * centres, and its derivative in z_A is the boundary term of total order p+1:
+ *   E_k = sum_{|a|+|b|=p} (1/a!) M_A^a ((-1)^|b| / b!) K^(a+b+e_k)(R) M_B^b,
+ * K = -G/r.  The particles' total orbital torque equals 1/2 the sum over
+ * ordered pairs of R x E.  E splits over A's members i as m_i e_i with
+ *   e_i,k = sum_{|a|+|b|=p} (1/a!) (x_i - z_A)^a ((-1)^|b| / b!) K^(a+b+e_k)(R) M_B^b,
+ * so the spin torque per unit mass
+ *   t_i = -1/2 sum over the M2L pairs (A <- B) of i's ancestors A of R x e_i
+ * makes sum_i m_i (x_i x g_i + t_i) vanish exactly, pair by pair, and is
+ * linear in rho like g.  Leaf pairs of monopoles carry no such term (every
+ * product above has a factor of order >= 1 that vanishes for them).
+ * Uniform trees; t[k * nsink + s] at the given leaf cells (dense indices).
+ */
+int oracle_amcorr_sinks(int L, int p, double theta, double h, double G, const double *rho, int64_t nsink,
+                        const int64_t *sinks, double *t)
+{
+    fmm F;
+    mset s1;
+    if (fmm_alloc(&F, L, p, theta, h, G) || mset_init(&s1, p + 1)) { fmm_free(&F); return -1; }
+    const tree *T = &F.T;
+    const mset *s = &F.s;
+    const int nc = s->n, n = nlev(L);
+    upward(&F, rho);
+#pragma omp parallel
+    {
+        double *D = malloc(sizeof(double) * (size_t)s1.n);
+        double *Rs = malloc(sizeof(double) * scratch_len(&s1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < nsink; ++q) {
+            const int64_t i = sinks[q];
+            const int ix = (int)(i % n), iy = (int)((i / n) % n), iz = (int)(i / ((int64_t)n * n));
+            double xi[3], zA[3], zB[3], R[3], d[3], tt[3] = {0.0, 0.0, 0.0};
+            centre(T, L, ix, iy, iz, xi);
+            for (int l = 0; l < L; ++l) {
+                const int nl = nlev(l), sh = L - l;
+                const int A[3] = {ix >> sh, iy >> sh, iz >> sh};
+                centre(T, l, A[0], A[1], A[2], zA);
+                for (int k = 0; k < 3; ++k) d[k] = xi[k] - zA[k];
+                box bx = m2l_candidates(T, l, A);
+                for (int bz = bx.lo[2]; bz <= bx.hi[2]; ++bz)
+                    for (int by = bx.lo[1]; by <= bx.hi[1]; ++by)
+                        for (int bxx = bx.lo[0]; bxx <= bx.hi[0]; ++bxx) {
+                            const int B[3] = {bxx, by, bz};
+                            if (!m2l_rule(T, l, A, B)) continue;
+                            centre(T, l, bxx, by, bz, zB);
+                            for (int k = 0; k < 3; ++k) R[k] = zA[k] - zB[k];
+                            inv_r_derivs(&s1, R[0], R[1], R[2], D, Rs);
+                            const double *MB = &F.M[l][cid(nl, bxx, by, bz) * nc];
+                            double e[3] = {0.0, 0.0, 0.0};
+                            for (int ia = 0; ia < nc; ++ia)
+                                for (int ib = 0; ib < nc; ++ib) {
+                                    if (s->order[ia] + s->order[ib] != p) continue;
+                                    const int *a = s->a[ia], *b = s->a[ib];
+                                    const double sgn = (s->order[ib] & 1) ? -1.0 : 1.0;
+                                    const double c = mpow(d, a[0], a[1], a[2]) * s->ifact[ia] * sgn * s->ifact[ib] * MB[ib];
+                                    for (int k = 0; k < 3; ++k)
+                                        e[k] += c * (-G) * D[mset_find(&s1, a[0] + b[0] + (k == 0), a[1] + b[1] + (k == 1),
+                                                                      a[2] + b[2] + (k == 2))];
+                                }
+                            tt[0] += -0.5 * (R[1] * e[2] - R[2] * e[1]);
+                            tt[1] += -0.5 * (R[2] * e[0] - R[0] * e[2]);
+                            tt[2] += -0.5 * (R[0] * e[1] - R[1] * e[0]);
+                        }
+            }
+            t[q] = tt[0]; t[nsink + q] = tt[1]; t[2 * nsink + q] = tt[2];
+        }
+        free(D); free(Rs);
+    }
+    mset_free(&s1);
+    fmm_free(&F);
+    return 0;
+}
