@@ -88,6 +88,9 @@ extern "C" {
                                         Results of different counts agree to
                                         rounding; a plan keeps its counts, so its
                                         calls repeat bit for bit. */
+#define OT_FMM_AM_CORRECTION (1u << 3) /* keep what ot_fmm_am_correction needs
+                                        (full moments at every level, order-4
+                                        kernel tables); uniform trees only */
 
 typedef struct ot_fmm_plan_s *ot_fmm_plan;   /* opaque */
 
@@ -149,6 +152,19 @@ int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order,
 /* phi[N], g[3N] <- FMM of rho[N] (device pointers, layout order). */
 int ot_fmm_forward(ot_fmm_plan plan, const double *rho, double *phi, double *g,
                    void *hip_stream);
+
+/* Angular-momentum correction (Sec. 4.3 names it; the formula is this
+ * library's reading).  The truncated M2L conserves linear momentum but not
+ * angular momentum: for an M2L pair (A <- B), R = z_A - z_B, the particles'
+ * torque is R x E/2 per ordered pair, E being the pair energy's derivative in
+ * the expansion centre z_A (its terms of total order p + 1).  t[3N] <- the
+ * spin torque per unit mass that takes it back:
+ *   t_i = -1/2 sum over the M2L pairs (A <- B) of cell i's ancestors of R x e_i,
+ * e_i cell i's share of E per unit mass, so that sum_i m_i (x_i x g_i + t_i)
+ * = 0 exactly with g from ot_fmm_forward on the same rho; t is linear in rho.
+ * Needs a plan created with OT_FMM_AM_CORRECTION (else INVALID_ARGUMENT); runs
+ * its own upward pass.  FP64. */
+int ot_fmm_am_correction(ot_fmm_plan plan, const double *rho, double *t, void *hip_stream);
 
 /* drho[N] <- transpose of the forward operator applied to (dphi[N], dg[3N]). */
 int ot_fmm_adjoint(ot_fmm_plan plan, const double *dphi, const double *dg,

@@ -307,6 +307,49 @@ void cf_table_down(int r2i, double h, double G, std::vector<double> &K)
 // leaves or all refined cells of one sub-grid; rows at levels 0 and 1
 Block amr_block(int l) { return block_shape(4 << l, (4 << l) >= 16); }
 
+// Angular-momentum correction table, per level l < L and offset o (source
+// minus sink, R = -o h_l): KX[c][j] = -1/2 (R x K^(c+e))_j for the 10
+// order-3 components c, K = -G/r, from the closed form of the fourth
+// derivatives of 1/r:
+//   d_ijkl (1/r) = 105 x_i x_j x_k x_l / r^9
+//                  - 15 (d_ij x_k x_l + 5 more pairings) / r^7 + 3 (d_ij d_kl + 2 more) / r^5
+void am_table(ot_fmm_plan P)
+{
+    const int L = P->L;
+    static const int three[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
+                                     {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
+    auto dl = [](int i, int j) { return i == j ? 1.0 : 0.0; };
+    P->KX.assign((size_t)std::max(L, 1) * OFF_N * 30, 0.0);
+    for (int l = 0; l < L; ++l) {
+        const double hl = P->h * (double)(1 << (L - l));
+        for (int oz = -OFF_R; oz <= OFF_R; ++oz)
+            for (int oy = -OFF_R; oy <= OFF_R; ++oy)
+                for (int ox = -OFF_R; ox <= OFF_R; ++ox) {
+                    if (!ox && !oy && !oz) continue;
+                    const double X[3] = {-ox * hl, -oy * hl, -oz * hl};
+                    const double r2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2], r = std::sqrt(r2);
+                    const double i5 = 1.0 / (r2 * r2 * r), i7 = i5 / r2, i9 = i7 / r2;
+                    auto K4 = [&](int i, int j, int k, int m) {
+                        const double t = 105.0 * X[i] * X[j] * X[k] * X[m] * i9 -
+                                         15.0 * (dl(i, j) * X[k] * X[m] + dl(i, k) * X[j] * X[m] +
+                                                 dl(i, m) * X[j] * X[k] + dl(j, k) * X[i] * X[m] +
+                                                 dl(j, m) * X[i] * X[k] + dl(k, m) * X[i] * X[j]) * i7 +
+                                         3.0 * (dl(i, j) * dl(k, m) + dl(i, k) * dl(j, m) + dl(i, m) * dl(j, k)) * i5;
+                        return -P->G * t;
+                    };
+                    double *row = &P->KX[((size_t)l * OFF_N + off_index(ox, oy, oz)) * 30];
+                    for (int c = 0; c < 10; ++c) {
+                        const int i = three[c][0], j = three[c][1], k = three[c][2];
+                        double Ke[3];
+                        for (int e = 0; e < 3; ++e) Ke[e] = K4(i, j, k, e);
+                        row[3 * c + 0] = -0.5 * (X[1] * Ke[2] - X[2] * Ke[1]);
+                        row[3 * c + 1] = -0.5 * (X[2] * Ke[0] - X[0] * Ke[2]);
+                        row[3 * c + 2] = -0.5 * (X[0] * Ke[1] - X[1] * Ke[0]);
+                    }
+                }
+    }
+}
+
 // Blocks (64 parents of shape bs) of level l that hold a parent of a listed
 // sub-grid's cells
 std::vector<int32_t> blocks_of(int l, const std::vector<int32_t> &nodes, Block bs)
@@ -974,6 +1017,7 @@ int setup_device(ot_fmm_plan P)
         bool full = false;
         for (int i = 1; i < d.n_span; ++i) full = full || (l == d.span_top[i]);
         if (P->amr) full = l >= 1 && !P->rnodes[l].empty();     // the M2M of level l - 1 reads them
+        if (P->flags & OT_FMM_AM_CORRECTION) full = true;       // the correction reads every level's
         v.M = nullptr;
         v.Mr = nullptr;
         v.M32 = nullptr;
@@ -989,6 +1033,19 @@ int setup_device(ot_fmm_plan P)
         if ((rc = dev_alloc(P, &v.Cp, (size_t)std::max(v.maxp, 1) * NC * 8 * np3, true))) return rc;
     }
     if (P->amr && (rc = setup_amr_views(P, G))) return rc;
+    if (P->flags & OT_FMM_AM_CORRECTION) {
+        am_table(P);
+        if ((rc = dev_upload(P, &P->dev_KX, P->KX))) return rc;
+        std::vector<double *> pis(std::max(L, 1), nullptr);
+        for (int l = 0; l < L; ++l) {
+            const size_t np3 = (size_t)d.lev[l].np * d.lev[l].np * d.lev[l].np;
+            if ((rc = dev_alloc(P, &P->Pi[l], (size_t)3 * NC * 8 * np3, true))) return rc;
+            pis[l] = P->Pi[l];
+        }
+        double *const *dpi = nullptr;                 // the per-level pointers, in device memory
+        if ((rc = dev_upload(P, &dpi, pis))) return rc;
+        P->dev_Pi = dpi;
+    }
     // stencil chunks of the leaf passes: the smallest power of two that gives
     // a launch at least 16384 waves (four rounds of the 4096 wave slots the
     // leaf kernels' registers leave), at most LEAF_MAX_CHUNKS per block.  The
@@ -1279,7 +1336,7 @@ int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order, 
 {
     if (!out) return fail(OT_FMM_INVALID_ARGUMENT, "out is NULL");
     *out = nullptr;
-    if (flags & ~(OT_FMM_HOST_ONLY | OT_FMM_M2L_FP32 | OT_FMM_AUTOTUNE))
+    if (flags & ~(OT_FMM_HOST_ONLY | OT_FMM_M2L_FP32 | OT_FMM_AUTOTUNE | OT_FMM_AM_CORRECTION))
         return fail(OT_FMM_INVALID_ARGUMENT, "unknown flag bits");
     if (!std::isfinite(theta) || theta <= 0.0) return fail(OT_FMM_INVALID_ARGUMENT, "theta must be finite and > 0");
     if (!(theta > 1.0 / 3.0 && theta <= 1.0))
@@ -1294,6 +1351,10 @@ int ot_fmm_plan_create(const ot_octree_layout *layout, double theta, int order, 
     P->r2 = rn * rn;
     int rc = validate_layout(layout, P);
     if (rc) { delete P; return rc; }
+    if (P->amr && (flags & OT_FMM_AM_CORRECTION)) {
+        delete P;
+        return fail(OT_FMM_UNSUPPORTED_LAYOUT, "the angular-momentum correction is built for uniform trees only");
+    }
     try {
         build_tables(P);
         if (P->amr) build_amr_tables(P);
@@ -1381,6 +1442,25 @@ int ot_fmm_forward(ot_fmm_plan P, const double *rho, double *phi, double *g, voi
     }
     total.end();
     if (P->timing.active && P->timing.calls < P->timing.max_calls) P->timing.calls++;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_am_correction(ot_fmm_plan P, const double *rho, double *t, void *hip_stream)
+{
+    if (!P) return fail(OT_FMM_INVALID_ARGUMENT, "plan is NULL");
+    if (!P->has_device) return fail(OT_FMM_NO_DEVICE_STATE, "plan was created with OT_FMM_HOST_ONLY");
+    if (!(P->flags & OT_FMM_AM_CORRECTION))
+        return fail(OT_FMM_INVALID_ARGUMENT, "plan was created without OT_FMM_AM_CORRECTION");
+    if (!rho || !t) return fail(OT_FMM_INVALID_ARGUMENT, "NULL device pointer");
+    if (misaligned(rho) || misaligned(t)) return fail(OT_FMM_INVALID_ARGUMENT, "device pointers must be 8-byte aligned");
+    DeviceGuard guard(P->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const DevPlan &d = P->dp;
+    hipError_t e;
+    if ((e = launch_upward_leaf(d, rho, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf");
+    if ((e = launch_m2m_upper(d, s)) != hipSuccess) return hip_fail(e, "launch of the upper M2M spans");
+    if ((e = launch_am_correction(d, P->dev_KX, P->Pi, P->dev_Pi, t, s)) != hipSuccess)
+        return hip_fail(e, "launch of the angular-momentum correction");
     return OT_FMM_OK;
 }
 

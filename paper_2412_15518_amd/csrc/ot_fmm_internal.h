@@ -187,6 +187,11 @@ struct ot_fmm_plan_s {
     // read Mr_ref, with its own units, runs and pieces
     otfmm::DevPlan m2l_leaf{};
     bool has_m2l_leaf = false;
+    // angular-momentum correction (plan flag OT_FMM_AM_CORRECTION, uniform trees)
+    std::vector<double> KX;                            // [L][OFF_N][10][3]
+    const double *dev_KX = nullptr;
+    double *Pi[otfmm::MAX_LEVELS] = {};                // [3 * NC][8][np^3] per level
+    double *const *dev_Pi = nullptr;
     const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
     const uint8_t *dev_ntype[otfmm::MAX_LEVELS] = {};
     std::vector<int32_t> ulist[otfmm::MAX_LEVELS];    // M2L units computed, per level
@@ -222,6 +227,11 @@ hipError_t launch_amr_leaf_moments(const DevPlan &v, int adj, const int32_t *nod
 //   any plan whose lev[] is the tree's when level l + 1 holds no leaves)
 hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes, int n, const uint8_t *child_type,
                           const double *a0, const double *a1, hipStream_t s);
+// angular-momentum correction of a uniform plan whose levels keep full
+// moments (after its upward pass): Pi per level (Pi_host: the device pointers
+// of levels 0..L-1; Pi_dev: the same array in device memory), then t[3N]
+hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
+                                double *t, hipStream_t s);
 //   final local expansions of the n refined sub-grids of level l (p: the plan)
 hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s);
 //   for the leaves of level v.L: their own level's M2L part (below the finest

@@ -498,7 +498,7 @@ void k_m2m_span(const DevPlan p, const double *__restrict__ a0, const double *__
                 // the child is a leaf parent: P2M from its leaf sources, stored for the M2L
                 const int Qx = 2 * cx + (b & 1), Qy = 2 * cy + ((b >> 1) & 1), Qz = 2 * cz + (b >> 2);
                 leaf_p2m<SRC == 2>(p, a0, a1, Qx, Qy, Qz, Mc);
-                store_moments(p.lev[lv + 1], Qx, Qy, Qz, Mc, false);
+                store_moments(p.lev[lv + 1], Qx, Qy, Qz, Mc, p.lev[lv + 1].M != nullptr);
             } else if (j == nlev - 1) {
                 // the children of c are stored under c in level lv + 1
                 const DevLevel &Dc = p.lev[lv + 1];
@@ -1581,6 +1581,115 @@ __global__ __launch_bounds__(CF_WAVES * 64) void k_amr_cf(const DevPlan p, doubl
 }
 
 // ------------------------------------------------------------------------
+// Angular-momentum correction.  For an M2L pair (A <- B), R = z_A - z_B, the
+// truncated pair energy depends on the expansion centres through its
+// boundary term of total order p + 1 = 4; the correction is the spin torque
+// per unit mass t at each leaf cell x_i:
+//   t_i,j = sum over i's ancestors A and their M2L partners B of
+//           sum_a (x_i - z_A)^a / a! Pi_A^a_j,
+//   Pi_A^a_j = sum_B sum_{|a|+|b|=3} KX_j^(a+b)(R) Mt_B^b,
+//   KX_j^c = -1/2 (R x K^(c+e))_j = -1/2 eps_jkl R_k K^(c+e_l),
+// with Mt the scaled moments sum m (z - x)^b / b! (which carry the sign and
+// factorial of the source side) and K = -G/r.  sum_i m_i (x_i x g_i + t_i)
+// then vanishes exactly.
+// ------------------------------------------------------------------------
+struct AMTerm { int a, b, c; };      // sink order a, source order b, c = a + b (total order 3)
+struct AMTerms { AMTerm t[56]; int n; };
+constexpr AMTerms make_am_terms()
+{
+    AMTerms T{};
+    T.n = 0;
+    for (int a = 0; a < NC; ++a)
+        for (int b = 0; b < NC; ++b)
+            if (order_of(a) + order_of(b) == 3)
+                T.t[T.n++] = {a, b, comp_of(kMI[a].t + kMI[b].t, kMI[a].u + kMI[b].u, kMI[a].v + kMI[b].v)};
+    return T;
+}
+static_assert(make_am_terms().n == 56, "56 (a, b) pairs of total order 3");
+
+// Pi of every cell of level l (one thread per cell; cells of the level's
+// padded-parent layout): the M2L partners of the level's stencil
+__global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const double *__restrict__ KX,
+                                              double *__restrict__ Pi)
+{
+    const DevLevel &D = p.lev[l];
+    const int n = 2 * D.np;
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * n * n) return;
+    const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
+    const int b = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+    const int nP = l == 0 ? p.n_plist_cube : p.n_plist_near;
+    const char4 *plist = l == 0 ? p.plist_cube : p.plist_near;
+    const int64_t pp = D.pp, pp3 = pp * pp * pp, np = D.np, np3 = np * np * np;
+    const double *KXl = KX + (int64_t)l * OFF_N * 30;
+    double P3[3][NC];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int a = 0; a < NC; ++a) P3[j][a] = 0.0;
+    constexpr AMTerms T = make_am_terms();
+    for (int i = 0; i < nP; ++i) {
+        const char4 P = plist[i];
+        const int64_t pad = ((int64_t)((cz >> 1) + P.z + D.hp) * pp + ((cy >> 1) + P.y + D.hp)) * pp +
+                            ((cx >> 1) + P.x + D.hp);
+        for (int bp = 0; bp < 8; ++bp) {
+            const int ox = 2 * P.x + (bp & 1) - (cx & 1), oy = 2 * P.y + ((bp >> 1) & 1) - (cy & 1),
+                      oz = 2 * P.z + (bp >> 2) - (cz & 1);
+            if (ox * ox + oy * oy + oz * oz <= p.r2i) continue;          // near: one level down
+            double M[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) M[k] = D.M[(k * 8 + bp) * pp3 + pad];
+            const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30;    // [10 order-3 components][3]
+#pragma unroll
+            for (int q = 0; q < 56; ++q) {
+                const int c = T.t[q].c - 10;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) P3[j][T.t[q].a] = fma(K[3 * c + j], M[T.t[q].b], P3[j][T.t[q].a]);
+            }
+        }
+    }
+    const int64_t q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int a = 0; a < NC; ++a) Pi[((int64_t)(j * NC + a) * 8 + b) * np3 + q] = P3[j][a];
+}
+
+// t at every leaf cell: the ancestors' Pi evaluated at the cell centre
+__global__ __launch_bounds__(WG) void k_am_leaf(const DevPlan p, double *const *__restrict__ Pi, double *__restrict__ tout)
+{
+    const int n = 8 << p.L;
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * n * n) return;
+    const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int l = 0; l < p.L; ++l) {
+        const int sh = p.L - l;
+        const int ax = cx >> sh, ay = cy >> sh, az = cz >> sh;
+        const DevLevel &D = p.lev[l];
+        // leaf centre minus the ancestor's centre
+        const double x = (cx + 0.5) * p.hleaf - (ax + 0.5) * D.h, y = (cy + 0.5) * p.hleaf - (ay + 0.5) * D.h,
+                     z = (cz + 0.5) * p.hleaf - (az + 0.5) * D.h;
+        double e[NC];
+        taylor(x, y, z, e);
+        const int64_t np = D.np, np3 = np * np * np;
+        const int64_t q = ((int64_t)(az >> 1) * np + (ay >> 1)) * np + (ax >> 1);
+        const int b = (ax & 1) + 2 * (ay & 1) + 4 * (az & 1);
+        const double *Pl = Pi[l];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int a = 0; a < NC; ++a) acc[j] = fma(e[a], Pl[((int64_t)(j * NC + a) * 8 + b) * np3 + q], acc[j]);
+    }
+    const int64_t slot = p.leaf_slot[((int64_t)(cz >> 3) * p.sL + (cy >> 3)) * p.sL + (cx >> 3)];
+    const int64_t idx = slot * 512 + ((cz & 7) * 8 + (cy & 7)) * 8 + (cx & 7);
+    const int64_t N = p.n_leaf_cells;
+    tout[idx] = acc[0];
+    tout[N + idx] = acc[1];
+    tout[2 * N + idx] = acc[2];
+}
+
+// ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
@@ -1730,6 +1839,24 @@ hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, 
         hipLaunchKernelGGL(k_amr_cf<true>, dim3(v.nblist), dim3(CF_WAVES * 64), 0, s, v, out0, out1);
     else
         hipLaunchKernelGGL(k_amr_cf<false>, dim3(v.nblist), dim3(CF_WAVES * 64), 0, s, v, out0, out1);
+    return hipGetLastError();
+}
+
+}  // namespace otfmm
+
+namespace otfmm {
+
+hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
+                                double *t, hipStream_t s)
+{
+    for (int l = 0; l < p.L; ++l) {
+        const int64_t n = 8 << l;
+        hipLaunchKernelGGL(k_am_pi, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t n = 8 << p.L;
+    hipLaunchKernelGGL(k_am_leaf, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, Pi_dev, t);
     return hipGetLastError();
 }
 

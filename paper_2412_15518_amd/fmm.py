@@ -29,11 +29,12 @@ FLAG_FP64 = 0
 FLAG_HOST_ONLY = 1
 FLAG_M2L_FP32 = 2
 FLAG_AUTOTUNE = 4
+FLAG_AM_CORRECTION = 8
 
 NUM_PHASES = 8
 PHASES = ["upward_leaf", "m2m", "m2l", "l2l", "leaf", "upward_leaf_adj", "leaf_adj", "total"]
 
-EXPORTS = ["ot_fmm_plan_create", "ot_fmm_forward", "ot_fmm_adjoint", "ot_fmm_plan_info",
+EXPORTS = ["ot_fmm_plan_create", "ot_fmm_forward", "ot_fmm_adjoint", "ot_fmm_am_correction", "ot_fmm_plan_info",
            "ot_fmm_destroy", "ot_fmm_status_string", "ot_fmm_last_error", "ot_fmm_timing_begin",
            "ot_fmm_timing_end", "ot_fmm_phase_name", "ot_fmm_timing_phases", "ot_fmm_batch_create",
            "ot_fmm_batch_forward", "ot_fmm_batch_adjoint", "ot_fmm_batch_capture_forward",
@@ -85,6 +86,8 @@ def load_library():
     lib.ot_fmm_forward.restype = C.c_int
     lib.ot_fmm_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.ot_fmm_adjoint.restype = C.c_int
+    lib.ot_fmm_am_correction.argtypes = [vp, vp, vp, vp]
+    lib.ot_fmm_am_correction.restype = C.c_int
     lib.ot_fmm_plan_info.argtypes = [vp, C.POINTER(_Info)]
     lib.ot_fmm_plan_info.restype = C.c_int
     lib.ot_fmm_destroy.argtypes = [vp]
@@ -134,10 +137,11 @@ class Plan:
     All device memory is allocated here, on the current device; forward and
     adjoint only enqueue kernels on the current torch stream.  m2l_fp32 runs
     the M2L in FP32 with FP64 accumulation (OT_FMM_M2L_FP32); autotune times
-    the leaf passes' stencil chunk counts at creation (OT_FMM_AUTOTUNE)."""
+    the leaf passes' stencil chunk counts at creation (OT_FMM_AUTOTUNE);
+    am_correction keeps what am_correction() needs (OT_FMM_AM_CORRECTION)."""
 
     def __init__(self, layout, theta: float = 0.4, order: int = 3, host_only: bool = False,
-                 m2l_fp32: bool = False, autotune: bool = False):
+                 m2l_fp32: bool = False, autotune: bool = False, am_correction: bool = False):
         lib = load_library()
         self._keep = [np.ascontiguousarray(layout.level, dtype=np.int32),
                       np.ascontiguousarray(layout.coord, dtype=np.int32).reshape(-1),
@@ -155,7 +159,7 @@ class Plan:
         L.G = float(layout.G)
         self._handle = C.c_void_p()
         flags = ((FLAG_HOST_ONLY if host_only else FLAG_FP64) | (FLAG_M2L_FP32 if m2l_fp32 else 0)
-                 | (FLAG_AUTOTUNE if autotune else 0))
+                 | (FLAG_AUTOTUNE if autotune else 0) | (FLAG_AM_CORRECTION if am_correction else 0))
         _check(lib.ot_fmm_plan_create(C.byref(L), float(theta), int(order), flags, C.byref(self._handle)))
         self._keep = None
         self.layout = layout
@@ -211,6 +215,17 @@ class Plan:
             self._check_field(t, k, n)
         _check(load_library().ot_fmm_adjoint(self._handle, C.c_void_p(dphi.data_ptr()), C.c_void_p(dg.data_ptr()),
                                              C.c_void_p(drho.data_ptr()), self._stream()))
+
+    def am_correction(self, rho):
+        """rho [N] -> t [3, N]: the spin torque per unit mass of the
+        angular-momentum correction (ot_fmm_am_correction)."""
+        import torch
+        rho = rho.contiguous().reshape(-1)
+        self._check_field(rho, 1, "rho")
+        t = torch.empty((3, self.n_cells), dtype=torch.float64, device=rho.device)
+        _check(load_library().ot_fmm_am_correction(self._handle, C.c_void_p(rho.data_ptr()),
+                                                   C.c_void_p(t.data_ptr()), self._stream()))
+        return t
 
     def forward(self, rho):
         """rho [N] -> (phi [N], g [3, N]) in layout order."""

@@ -151,7 +151,7 @@ def test_flags():
     L.origin = (C.c_double * 3)(0.0, 0.0, 0.0)
     L.G = 1.0
     h = C.c_void_p()
-    for bad in (1 << 3, 1 << 31):
+    for bad in (1 << 4, 1 << 31):
         assert lib.ot_fmm_plan_create(C.byref(L), 0.4, 3, fmm.FLAG_HOST_ONLY | bad, C.byref(h)) == fmm.INVALID_ARGUMENT
         assert h.value is None
     for good in (fmm.FLAG_M2L_FP32, fmm.FLAG_AUTOTUNE, fmm.FLAG_M2L_FP32 | fmm.FLAG_AUTOTUNE):
@@ -286,3 +286,14 @@ def test_unbalanced_adaptive_layout_rejected():
     with pytest.raises(fmm.OTFMMError) as e:
         fmm.Plan(unbalanced_layout(), host_only=True)
     assert e.value.status == -5 and "2:1" in str(e.value)
+
+
+def test_am_correction_flag():
+    """OT_FMM_AM_CORRECTION is accepted on uniform trees and refused on
+    adaptive ones; the entry point refuses a host-only plan."""
+    p = fmm.Plan(W.uniform_layout(2), host_only=True, am_correction=True)
+    assert p.info()["depth"] == 2
+    p.close()
+    with pytest.raises(fmm.OTFMMError) as e:
+        fmm.Plan(W.small_amr("corner")["layout"], host_only=True, am_correction=True)
+    assert e.value.status == -5
