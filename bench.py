@@ -17,7 +17,9 @@ oracle (forward + adjoint) on a z-slab of the same workload.  `m2l_fp32` times
 the FP32 M2L plan on the same workload; `batch` times 16 independent small
 adaptive octrees plan by plan, as one batch over 4 streams and as HIP graph replays;
 `amr` times the adaptive-octree workload (leaves on levels 3..6 of a 512^3
-box) and, in the CPU-baseline leg, checks sampled cells against the oracle.
+box) and, in the CPU-baseline leg, checks sampled cells against the oracle;
+`am_correction` times the angular-momentum correction at 128^3 and reports
+the total torque with and without it.
 """
 import argparse
 import hashlib
@@ -226,6 +228,44 @@ def bench_amr(args):
     return out, state
 
 
+def bench_am(args, lay, rho_dense) -> dict:
+    """The angular-momentum correction at 128^3: time per call, and the total
+    torque of the forward's forces with and without the spin torques."""
+    import numpy as np
+    import torch
+
+    from paper_2412_15518_amd import fmm
+    plan = fmm.Plan(lay, am_correction=True)
+    rho = torch.from_numpy(lay.dense_to_layout(rho_dense)).cuda()
+    N = rho.numel()
+    t = torch.empty((3, N), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        t = plan.am_correction(rho)
+    k = max(3, min(args.steps, 20))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        t = plan.am_correction(rho)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / k
+    _, g = plan.forward(rho)
+    torch.cuda.synchronize()
+    n = rho_dense.shape[-1]
+    c = np.arange(n) + 0.5
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    X = lay.dense_to_layout(np.stack([x, y, z])).T
+    m = rho.cpu().numpy()
+    orb = np.cross(X, (m[None] * g.cpu().numpy()).T)
+    spin = (m[None] * t.cpu().numpy()).T
+    scale = float(np.abs(orb).sum())
+    log(f"angular-momentum correction: {ms:.3f} ms per call")
+    return {"ms_per_call": ms, "calls": k,
+            "orbital_torque_rel": float(np.abs(orb.sum(0)).max() / scale),
+            "with_spin_torque_rel": float(np.abs(orb.sum(0) + spin.sum(0)).max() / scale),
+            "note": "spin torque per unit mass t (3 per leaf cell), FP64; |sum m (x x g)| and "
+                    "|sum m (x x g + t)| over sum |m x x g|, g from the same plan's forward"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +277,8 @@ def main():
                     help="also time the batch of 16 independent octrees (0: skip)")
     ap.add_argument("--amr", type=int, default=1,
                     help="1: also time the adaptive-octree workload (1296 leaf sub-grids, levels 3..6)")
+    ap.add_argument("--am", type=int, default=1,
+                    help="1: also time the angular-momentum correction at 128^3")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before warmup, copy this many MiB device to device once: a plain copy "
                          "kernel of known traffic that calibrates HBM counter readings")
@@ -394,6 +436,8 @@ def main():
 
     if args.batch:
         out["batch"] = bench_batch(args)
+    if args.am:
+        out["am_correction"] = bench_am(args, lay, cfg["rho"])
     amr_state = None
     if args.amr:
         out["amr"], amr_state = bench_amr(args)

@@ -1607,52 +1607,76 @@ constexpr AMTerms make_am_terms()
 }
 static_assert(make_am_terms().n == 56, "56 (a, b) pairs of total order 3");
 
-// Pi of every cell of level l (one thread per cell; cells of the level's
-// padded-parent layout): the M2L partners of the level's stencil
+// Pi of the cells of level l.  WIDE = false (the deep levels): one thread per
+// cell, all three components (each partner's moments are loaded once).
+// WIDE = true (the few cells of the top levels): one workgroup per cell and
+// component j = blockIdx.y, whose threads split the partner list; the partial
+// sums meet by shuffles within a wave and through LDS across the waves, in a
+// fixed order.
+template <bool WIDE>
 __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const double *__restrict__ KX,
                                               double *__restrict__ Pi)
 {
+    constexpr int NJ = WIDE ? 1 : 3;               // components per thread
     const DevLevel &D = p.lev[l];
     const int n = 2 * D.np;
-    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (t >= (int64_t)n * n * n) return;
+    const int j0 = WIDE ? (int)blockIdx.y : 0;
+    const int64_t t = WIDE ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= (int64_t)n * n * n) return;           // WIDE: the whole workgroup
     const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
     const int b = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
     const int nP = l == 0 ? p.n_plist_cube : p.n_plist_near;
     const char4 *plist = l == 0 ? p.plist_cube : p.plist_near;
     const int64_t pp = D.pp, pp3 = pp * pp * pp, np = D.np, np3 = np * np * np;
     const double *KXl = KX + (int64_t)l * OFF_N * 30;
-    double P3[3][NC];
+    double P3[NJ][NC];
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int a = 0; a < NC; ++a) P3[j][a] = 0.0;
     constexpr AMTerms T = make_am_terms();
-    for (int i = 0; i < nP; ++i) {
-        const char4 P = plist[i];
+    const int k0 = WIDE ? (int)threadIdx.x : 0, dk = WIDE ? WG : 1;
+    for (int k = k0; k < nP * 8; k += dk) {
+        const char4 P = plist[k >> 3];
+        const int bp = k & 7;
+        const int ox = 2 * P.x + (bp & 1) - (cx & 1), oy = 2 * P.y + ((bp >> 1) & 1) - (cy & 1),
+                  oz = 2 * P.z + (bp >> 2) - (cz & 1);
+        if (ox * ox + oy * oy + oz * oz <= p.r2i) continue;          // near: one level down
         const int64_t pad = ((int64_t)((cz >> 1) + P.z + D.hp) * pp + ((cy >> 1) + P.y + D.hp)) * pp +
                             ((cx >> 1) + P.x + D.hp);
-        for (int bp = 0; bp < 8; ++bp) {
-            const int ox = 2 * P.x + (bp & 1) - (cx & 1), oy = 2 * P.y + ((bp >> 1) & 1) - (cy & 1),
-                      oz = 2 * P.z + (bp >> 2) - (cz & 1);
-            if (ox * ox + oy * oy + oz * oz <= p.r2i) continue;          // near: one level down
-            double M[NC];
+        double M[NC];
 #pragma unroll
-            for (int k = 0; k < NC; ++k) M[k] = D.M[(k * 8 + bp) * pp3 + pad];
-            const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30;    // [10 order-3 components][3]
+        for (int q = 0; q < NC; ++q) M[q] = D.M[(q * 8 + bp) * pp3 + pad];
+        const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30 + j0;   // [10 order-3 components][3]
 #pragma unroll
-            for (int q = 0; q < 56; ++q) {
-                const int c = T.t[q].c - 10;
+        for (int q = 0; q < 56; ++q)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) P3[j][T.t[q].a] = fma(K[3 * c + j], M[T.t[q].b], P3[j][T.t[q].a]);
-            }
+            for (int j = 0; j < NJ; ++j)
+                P3[j][T.t[q].a] = fma(K[3 * (T.t[q].c - 10) + j], M[T.t[q].b], P3[j][T.t[q].a]);
+    }
+    if constexpr (WIDE) {
+        __shared__ double part[WG / 64][NC];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            double v = P3[0][a];
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_down(v, o, 64);
+            if (lane == 0) part[w][a] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x != 0) return;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            double v = part[0][a];
+            for (int x = 1; x < WG / 64; ++x) v += part[x][a];
+            P3[0][a] = v;
         }
     }
     const int64_t q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
-        for (int a = 0; a < NC; ++a) Pi[((int64_t)(j * NC + a) * 8 + b) * np3 + q] = P3[j][a];
+        for (int a = 0; a < NC; ++a) Pi[((int64_t)((j0 + j) * NC + a) * 8 + b) * np3 + q] = P3[j][a];
 }
 
 // t at every leaf cell: the ancestors' Pi evaluated at the cell centre
@@ -1851,7 +1875,10 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
 {
     for (int l = 0; l < p.L; ++l) {
         const int64_t n = 8 << l;
-        hipLaunchKernelGGL(k_am_pi, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
+        if (l <= 1)      // 512 and 4096 cells: a workgroup per cell and component
+            hipLaunchKernelGGL(k_am_pi<true>, dim3((unsigned)(n * n * n), 3), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
+        else
+            hipLaunchKernelGGL(k_am_pi<false>, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
