@@ -1679,6 +1679,67 @@ __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const doub
         for (int a = 0; a < NC; ++a) Pi[((int64_t)((j0 + j) * NC + a) * 8 + b) * np3 + q] = P3[j][a];
 }
 
+// Pi of the cells of the deeper levels, organised like the M2L: a workgroup
+// of 8 waves owns a block of 64 parents (lane = parent) and wave w its sink
+// child w; for each source (parent offset P, child b') the 64 parents'
+// 20 moments are staged once in LDS for the 8 waves, and the kernel row,
+// which depends only on the offset 2P + b' - w, is the same for the whole wave.
+constexpr int AM_WG = 512;
+__global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, const double *__restrict__ KX,
+                                                      double *__restrict__ Pi)
+{
+    __shared__ double tile[NC][64];
+    const DevLevel &D = p.lev[l];
+    const int np = D.np;
+    const Block bs = block_shape(np);
+    const int nbx = np / bs.bx, nby = np / bs.by, nbz = np / bs.bz;
+    const int blk = blockIdx.x;
+    if (blk >= nbx * nby * nbz) return;               // the whole workgroup
+    const int lane = threadIdx.x & 63;
+    const int w = uniform(threadIdx.x >> 6);           // sink child
+    const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
+    const int Qy = ((blk / nbx) % nby) * bs.by + (lane / bs.bx) % bs.by;
+    const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
+    const int nP = p.n_plist_near;
+    const int64_t pp = D.pp, pp3 = pp * pp * pp, np3 = (int64_t)np * np * np;
+    const double *KXl = KX + (int64_t)l * OFF_N * 30;
+    double P3[3][NC];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int a = 0; a < NC; ++a) P3[j][a] = 0.0;
+    constexpr AMTerms T = make_am_terms();
+    for (int i = 0; i < nP; ++i) {
+        const char4 P = p.plist_near[i];
+        const int64_t pad = ((int64_t)(Qz + P.z + D.hp) * pp + (Qy + P.y + D.hp)) * pp + (Qx + P.x + D.hp);
+        for (int bp = 0; bp < 8; ++bp) {
+            // stage the 64 parents' moments of source child bp: wave w loads
+            // components w, w + 8, w + 16
+            for (int c = w; c < NC; c += 8) tile[c][lane] = D.M[(c * 8 + bp) * pp3 + pad];
+            __syncthreads();
+            const int ox = 2 * P.x + (bp & 1) - (w & 1), oy = 2 * P.y + ((bp >> 1) & 1) - ((w >> 1) & 1),
+                      oz = 2 * P.z + (bp >> 2) - (w >> 2);
+            if (ox * ox + oy * oy + oz * oz > p.r2i) {       // far (wave-uniform): one level down otherwise
+                const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30;
+                double M[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) M[c] = tile[c][lane];
+#pragma unroll
+                for (int q = 0; q < 56; ++q)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        P3[j][T.t[q].a] = fma(K[3 * (T.t[q].c - 10) + j], M[T.t[q].b], P3[j][T.t[q].a]);
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t q = ((int64_t)Qz * np + Qy) * np + Qx;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int a = 0; a < NC; ++a) Pi[((int64_t)(j * NC + a) * 8 + w) * np3 + q] = P3[j][a];
+}
+
 // t at every leaf cell: the ancestors' Pi evaluated at the cell centre
 __global__ __launch_bounds__(WG) void k_am_leaf(const DevPlan p, double *const *__restrict__ Pi, double *__restrict__ tout)
 {
@@ -1875,10 +1936,15 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
 {
     for (int l = 0; l < p.L; ++l) {
         const int64_t n = 8 << l;
-        if (l <= 1)      // 512 and 4096 cells: a workgroup per cell and component
+        // measured at 128^3: a workgroup per cell and component for the 512 and
+        // 4096 cells of levels 0 and 1, a thread per cell at level 2 (0.70 ms
+        // against 0.96 tiled), the tiled form from level 3 on (2.2 against 2.6 ms)
+        if (l <= 1)
             hipLaunchKernelGGL(k_am_pi<true>, dim3((unsigned)(n * n * n), 3), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
-        else
+        else if (l == 2)
             hipLaunchKernelGGL(k_am_pi<false>, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
+        else
+            hipLaunchKernelGGL(k_am_pi_tile, dim3((unsigned)(n * n * n / 512)), dim3(AM_WG), 0, s, p, l, KX, Pi_host[l]);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
