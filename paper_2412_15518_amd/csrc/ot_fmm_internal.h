@@ -192,6 +192,7 @@ struct ot_fmm_plan_s {
     const double *dev_KX = nullptr;
     double *Pi[otfmm::MAX_LEVELS] = {};                // [3 * NC][8][np^3] per level
     double *const *dev_Pi = nullptr;
+    int am_tiled = 0;                                  // the device gives a workgroup AM_TILE_LDS of LDS
     const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
     const uint8_t *dev_ntype[otfmm::MAX_LEVELS] = {};
     std::vector<int32_t> ulist[otfmm::MAX_LEVELS];    // M2L units computed, per level
@@ -231,7 +232,9 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 // moments (after its upward pass): Pi per level (Pi_host: the device pointers
 // of levels 0..L-1; Pi_dev: the same array in device memory), then t[3N]
 hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
-                                double *t, hipStream_t s);
+                                double *t, int tiled, hipStream_t s);
+// LDS bytes of the tiled Pi kernel (tiled = 1 needs this much per workgroup)
+constexpr size_t AM_TILE_LDS = (size_t)8 * NC * 64 * sizeof(double);
 //   final local expansions of the n refined sub-grids of level l (p: the plan)
 hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s);
 //   for the leaves of level v.L: their own level's M2L part (below the finest

@@ -1681,14 +1681,15 @@ __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const doub
 
 // Pi of the cells of the deeper levels, organised like the M2L: a workgroup
 // of 8 waves owns a block of 64 parents (lane = parent) and wave w its sink
-// child w; for each source (parent offset P, child b') the 64 parents'
-// 20 moments are staged once in LDS for the 8 waves, and the kernel row,
-// which depends only on the offset 2P + b' - w, is the same for the whole wave.
+// child w.  For each parent offset P the moments of the 8 source children of
+// the 64 parents Q + P are staged once in LDS (wave w loads child w's) for
+// all 8 waves, and the kernel row of a (P, b') pair, which depends only on
+// the offset 2P + b' - w, is the same for the whole wave.
 constexpr int AM_WG = 512;
 __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, const double *__restrict__ KX,
                                                       double *__restrict__ Pi)
 {
-    __shared__ double tile[NC][64];
+    extern __shared__ double tile[];                   // [8 source children][NC][64]
     const DevLevel &D = p.lev[l];
     const int np = D.np;
     const Block bs = block_shape(np);
@@ -1696,7 +1697,7 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
     const int blk = blockIdx.x;
     if (blk >= nbx * nby * nbz) return;               // the whole workgroup
     const int lane = threadIdx.x & 63;
-    const int w = uniform(threadIdx.x >> 6);           // sink child
+    const int w = uniform(threadIdx.x >> 6);           // sink child, and the source child this wave stages
     const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
     const int Qy = ((blk / nbx) % nby) * bs.by + (lane / bs.bx) % bs.by;
     const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
@@ -1712,26 +1713,24 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
     for (int i = 0; i < nP; ++i) {
         const char4 P = p.plist_near[i];
         const int64_t pad = ((int64_t)(Qz + P.z + D.hp) * pp + (Qy + P.y + D.hp)) * pp + (Qx + P.x + D.hp);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) tile[(w * NC + c) * 64 + lane] = D.M[(c * 8 + w) * pp3 + pad];
+        __syncthreads();
         for (int bp = 0; bp < 8; ++bp) {
-            // stage the 64 parents' moments of source child bp: wave w loads
-            // components w, w + 8, w + 16
-            for (int c = w; c < NC; c += 8) tile[c][lane] = D.M[(c * 8 + bp) * pp3 + pad];
-            __syncthreads();
             const int ox = 2 * P.x + (bp & 1) - (w & 1), oy = 2 * P.y + ((bp >> 1) & 1) - ((w >> 1) & 1),
                       oz = 2 * P.z + (bp >> 2) - (w >> 2);
-            if (ox * ox + oy * oy + oz * oz > p.r2i) {       // far (wave-uniform): one level down otherwise
-                const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30;
-                double M[NC];
+            if (ox * ox + oy * oy + oz * oz <= p.r2i) continue;     // near (wave-uniform): one level down
+            const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30;
+            double M[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) M[c] = tile[c][lane];
+            for (int c = 0; c < NC; ++c) M[c] = tile[(bp * NC + c) * 64 + lane];
 #pragma unroll
-                for (int q = 0; q < 56; ++q)
+            for (int q = 0; q < 56; ++q)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j)
-                        P3[j][T.t[q].a] = fma(K[3 * (T.t[q].c - 10) + j], M[T.t[q].b], P3[j][T.t[q].a]);
-            }
-            __syncthreads();
+                for (int j = 0; j < 3; ++j)
+                    P3[j][T.t[q].a] = fma(K[3 * (T.t[q].c - 10) + j], M[T.t[q].b], P3[j][T.t[q].a]);
         }
+        __syncthreads();
     }
     const int64_t q = ((int64_t)Qz * np + Qy) * np + Qx;
 #pragma unroll
@@ -1932,7 +1931,7 @@ hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, 
 namespace otfmm {
 
 hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
-                                double *t, hipStream_t s)
+                                double *t, int tiled, hipStream_t s)
 {
     for (int l = 0; l < p.L; ++l) {
         const int64_t n = 8 << l;
@@ -1941,10 +1940,11 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
         // against 0.96 tiled), the tiled form from level 3 on (2.2 against 2.6 ms)
         if (l <= 1)
             hipLaunchKernelGGL(k_am_pi<true>, dim3((unsigned)(n * n * n), 3), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
-        else if (l == 2)
+        else if (l == 2 || !tiled)
             hipLaunchKernelGGL(k_am_pi<false>, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
         else
-            hipLaunchKernelGGL(k_am_pi_tile, dim3((unsigned)(n * n * n / 512)), dim3(AM_WG), 0, s, p, l, KX, Pi_host[l]);
+            hipLaunchKernelGGL(k_am_pi_tile, dim3((unsigned)(n * n * n / 512)), dim3(AM_WG),
+                               AM_TILE_LDS, s, p, l, KX, Pi_host[l]);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -47,6 +47,17 @@ def test_whole_grid_matches_oracle(L, kind):
     assert normwise_vec(t.reshape(3, -1), to.reshape(3, -1)) < TOL
 
 
+def test_fp32_m2l_plan_gives_the_same_t():
+    """The correction reads only the FP64 upward pass: an FP32-M2L plan
+    returns the same bits."""
+    lay = W.uniform_layout(3)
+    rho = torch.from_numpy(lay.dense_to_layout(W.random_density(64, 35))).cuda()
+    t64 = fmm.Plan(lay, am_correction=True).am_correction(rho)
+    t32 = fmm.Plan(lay, am_correction=True, m2l_fp32=True).am_correction(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(t64, t32)
+
+
 def test_single_subgrid_is_zero():
     lay = W.uniform_layout(0)
     t = gpu_t(lay, W.random_density(8, 33))
