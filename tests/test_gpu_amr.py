@@ -59,6 +59,19 @@ def test_forward_whole_tree(kind):
     assert normwise_vec(g, go) < TOL
 
 
+@pytest.mark.parametrize("theta", [0.34, 0.6])
+def test_forward_other_opening_angles(theta):
+    """Near radius 2.94 and 1.67 cells: other stencils, coarse-fine reaches and
+    tables, against the oracle on the whole tree."""
+    d = W.small_amr("edge")
+    lay, rho = d["layout"], d["rho"]
+    say("amr forward theta", theta)
+    phi, g = forward(fmm.Plan(lay, theta=theta), rho)
+    po, go = O.amr_fmm_sinks(lay, rho, theta=theta)
+    assert normwise(phi, po) < TOL
+    assert normwise_vec(g, go) < TOL
+
+
 def test_forward_sampled_sinks_three_levels():
     d = W.small_amr("blob")
     lay, rho = d["layout"], d["rho"]

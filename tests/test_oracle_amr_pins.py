@@ -50,6 +50,14 @@ def test_pair_cover_exact(kind, nsample):
         assert np.all(np.delete(m, s) == 1), (s, np.unique(m, return_counts=True))
 
 
+@pytest.mark.parametrize("theta", [0.34, 0.6])
+def test_pair_cover_other_opening_angles(theta):
+    lay = W.small_amr("edge")["layout"]
+    for s in np.random.default_rng(13).choice(lay.n_leaf_cells, 60, replace=False):
+        m = O.amr_cover(lay, s, theta=theta)
+        assert m[s] == 0 and np.all(np.delete(m, s) == 1), (theta, s)
+
+
 def test_pair_cover_workload_sample():
     d = W.adaptive_two_polytropes(with_cotangents=False)
     lay = d["layout"]
