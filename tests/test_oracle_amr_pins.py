@@ -192,3 +192,33 @@ def test_workload_tree():
     assert len(np.unique(lay.level[lay.leaf_nodes])) == 4
     assert _touching_leaf_levels_ok(lay)
     assert d["rho"].shape == (lay.n_leaf_cells,) and d["rho"].min() > 0
+
+
+def test_direct_sum_two_masses_on_different_levels():
+    """The adaptive direct sum itself: two point masses on levels 1 and 2 give
+    -G m / r and -G m r_hat / r^2 exactly, with h_l = h 2^(L - l)."""
+    d = W.small_amr("corner")
+    lay = d["layout"]
+    G, h = 0.7, 0.25
+    lay.G, lay.h_leaf_min = G, h
+    rho = np.zeros(lay.n_leaf_cells)
+    ia, ib = _mass_in(lay, 1, (12, 3, 9)), _mass_in(lay, 2, (2, 13, 5))
+    rho[ia], rho[ib] = 1.5, 0.25
+    xa, xb = (np.array([12, 3, 9]) + 0.5) * 2 * h, (np.array([2, 13, 5]) + 0.5) * h
+    ma, mb = 1.5 * (2 * h) ** 3, 0.25 * h ** 3
+    r = xa - xb
+    dist = np.linalg.norm(r)
+    phi, g = O.amr_direct(lay, rho, [ia, ib])
+    assert phi[0] == pytest.approx(-G * mb / dist, rel=1e-14)
+    assert phi[1] == pytest.approx(-G * ma / dist, rel=1e-14)
+    np.testing.assert_allclose(g[:, 0], -G * mb * r / dist ** 3, rtol=1e-13)
+    np.testing.assert_allclose(g[:, 1], G * ma * r / dist ** 3, rtol=1e-13)
+
+
+def test_direct_sum_uniform_tree_matches_dense_direct_sum():
+    lay = W.uniform_layout(1, order="random", seed=8)
+    rho_d = W.random_density(16, 9)
+    phi, g = O.amr_direct(lay, lay.dense_to_layout(rho_d))
+    pd, gd = O.direct(rho_d)
+    assert normwise(phi, lay.dense_to_layout(pd)) < 1e-14
+    assert normwise_vec(g, lay.dense_to_layout(gd)) < 1e-14
