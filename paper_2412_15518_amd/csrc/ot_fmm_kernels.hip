@@ -1607,35 +1607,31 @@ constexpr AMTerms make_am_terms()
 }
 static_assert(make_am_terms().n == 56, "56 (a, b) pairs of total order 3");
 
-// Pi of the cells of level l.  WIDE = false (the deep levels): one thread per
-// cell, all three components (each partner's moments are loaded once).
-// WIDE = true (the few cells of the top levels): one workgroup per cell and
-// component j = blockIdx.y, whose threads split the partner list; the partial
-// sums meet by shuffles within a wave and through LDS across the waves, in a
+// Pi of the cells of level l, all three components.  WIDE = false: one
+// thread per cell.  WIDE = true (levels with few cells): one wave per cell,
+// whose lanes split the partner list; the partial sums meet by shuffles in a
 // fixed order.
 template <bool WIDE>
 __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const double *__restrict__ KX,
                                               double *__restrict__ Pi)
 {
-    constexpr int NJ = WIDE ? 1 : 3;               // components per thread
     const DevLevel &D = p.lev[l];
     const int n = 2 * D.np;
-    const int j0 = WIDE ? (int)blockIdx.y : 0;
     const int64_t t = WIDE ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (t >= (int64_t)n * n * n) return;           // WIDE: the whole workgroup
+    if (t >= (int64_t)n * n * n) return;           // WIDE: the whole wave
     const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
     const int b = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
     const int nP = l == 0 ? p.n_plist_cube : p.n_plist_near;
     const char4 *plist = l == 0 ? p.plist_cube : p.plist_near;
     const int64_t pp = D.pp, pp3 = pp * pp * pp, np = D.np, np3 = np * np * np;
     const double *KXl = KX + (int64_t)l * OFF_N * 30;
-    double P3[NJ][NC];
+    double P3[3][NC];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int a = 0; a < NC; ++a) P3[j][a] = 0.0;
     constexpr AMTerms T = make_am_terms();
-    const int k0 = WIDE ? (int)threadIdx.x : 0, dk = WIDE ? WG : 1;
+    const int k0 = WIDE ? (int)threadIdx.x : 0, dk = WIDE ? 64 : 1;
     for (int k = k0; k < nP * 8; k += dk) {
         const char4 P = plist[k >> 3];
         const int bp = k & 7;
@@ -1647,36 +1643,26 @@ __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const doub
         double M[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) M[q] = D.M[(q * 8 + bp) * pp3 + pad];
-        const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30 + j0;   // [10 order-3 components][3]
+        const double *K = KXl + (int64_t)off_index(ox, oy, oz) * 30;   // [10 order-3 components][3]
 #pragma unroll
         for (int q = 0; q < 56; ++q)
 #pragma unroll
-            for (int j = 0; j < NJ; ++j)
+            for (int j = 0; j < 3; ++j)
                 P3[j][T.t[q].a] = fma(K[3 * (T.t[q].c - 10) + j], M[T.t[q].b], P3[j][T.t[q].a]);
     }
     if constexpr (WIDE) {
-        __shared__ double part[WG / 64][NC];
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-        for (int a = 0; a < NC; ++a) {
-            double v = P3[0][a];
-            for (int o = 32; o >= 1; o >>= 1) v += __shfl_down(v, o, 64);
-            if (lane == 0) part[w][a] = v;
-        }
-        __syncthreads();
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+                for (int o = 32; o >= 1; o >>= 1) P3[j][a] += __shfl_down(P3[j][a], o, 64);
         if (threadIdx.x != 0) return;
-#pragma unroll
-        for (int a = 0; a < NC; ++a) {
-            double v = part[0][a];
-            for (int x = 1; x < WG / 64; ++x) v += part[x][a];
-            P3[0][a] = v;
-        }
     }
     const int64_t q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int a = 0; a < NC; ++a) Pi[((int64_t)((j0 + j) * NC + a) * 8 + b) * np3 + q] = P3[j][a];
+        for (int a = 0; a < NC; ++a) Pi[((int64_t)(j * NC + a) * 8 + b) * np3 + q] = P3[j][a];
 }
 
 // Pi of the cells of the deeper levels, organised like the M2L: a workgroup
@@ -1935,11 +1921,13 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
 {
     for (int l = 0; l < p.L; ++l) {
         const int64_t n = 8 << l;
-        // measured at 128^3: a workgroup per cell and component for the 512 and
-        // 4096 cells of levels 0 and 1, a thread per cell at level 2 (0.70 ms
-        // against 0.96 tiled), the tiled form from level 3 on (2.2 against 2.6 ms)
+        // measured at 128^3: a wave per cell for the 512 and 4096 cells of
+        // levels 0 and 1 (81 and 176 us), a thread per cell at level 2 (0.70 ms;
+        // a wave per cell 1.25, tiled 0.96), the tiled form from level 3 on
+        // (1.58 ms against 2.6 with a thread per cell, which stays where the
+        // device's LDS is too small)
         if (l <= 1)
-            hipLaunchKernelGGL(k_am_pi<true>, dim3((unsigned)(n * n * n), 3), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
+            hipLaunchKernelGGL(k_am_pi<true>, dim3((unsigned)(n * n * n)), dim3(64), 0, s, p, l, KX, Pi_host[l]);
         else if (l == 2 || !tiled)
             hipLaunchKernelGGL(k_am_pi<false>, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
         else
