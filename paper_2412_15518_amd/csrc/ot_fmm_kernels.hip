@@ -322,6 +322,60 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
 // moments.  Forward: point masses m = rho h^3.  Adjoint: the dual sources, a
 // monopole w and a scaled dipole +u at each leaf centre.
 // ------------------------------------------------------------------------
+// The same P2M one leaf child at a time (adaptive trees' M2M, a lane per
+// child).  LeafQ: where the leaf children of Q sit: their sub-grid's first leaf
+// index, Q's padded source-plane index, the children's first coordinates in the
+// sub-grid
+struct LeafQ {
+    int64_t base, padQ, ppL3, N;
+    double hh;
+    int lx0, ly0, lz0;
+};
+__device__ __forceinline__ LeafQ leaf_q(const DevPlan &p, int Qx, int Qy, int Qz)
+{
+    LeafQ q;
+    q.padQ = ((int64_t)(Qz + p.hpL) * p.ppL + (Qy + p.hpL)) * p.ppL + (Qx + p.hpL);
+    q.base = (int64_t)p.leaf_slot[((int64_t)(Qz >> 2) * p.sL + (Qy >> 2)) * p.sL + (Qx >> 2)] * 512;
+    q.lx0 = (2 * Qx) & 7; q.ly0 = (2 * Qy) & 7; q.lz0 = (2 * Qz) & 7;
+    q.ppL3 = (int64_t)p.ppL * p.ppL * p.ppL;
+    q.N = p.n_leaf_cells;
+    q.hh = 0.5 * p.hleaf;
+    return q;
+}
+
+// leaf child b of Q (its x, y, z bits: b & 1, (b >> 1) & 1, b >> 2): stage its
+// sources and add its moments about Q's centre to Mq
+template <bool ADJ>
+__device__ __forceinline__ void leaf_p2m_child(const DevPlan &p, const double *__restrict__ a0,
+                                               const double *__restrict__ a1, const LeafQ &q, int b, double *Mq)
+{
+    const int64_t ppL3 = q.ppL3, N = q.N;
+    const double hh = q.hh;
+    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+    const int64_t idx = q.base + ((q.lz0 + bz) * 8 + (q.ly0 + by)) * 8 + (q.lx0 + bx);
+    double e[NC];
+    taylor(bx ? -hh : hh, by ? -hh : hh, bz ? -hh : hh, e);    // e(z_Q - z_child)
+    // source planes [plane][child pair][parent][2]: one 16-byte load of
+    // 64 neighbouring parents reads 1 KB of contiguous memory
+    const int64_t sp = ((b >> 1) * ppL3 + q.padQ) * 2 + (b & 1);
+    if (!ADJ) {
+        const double m = a0[idx] * p.h3;
+        p.src[sp] = m;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], m, Mq[k]);
+    } else {
+        const double w = a0[idx];
+        double u[3] = {a1[idx], a1[N + idx], a1[2 * N + idx]};
+        p.src[sp] = w;
+        p.src[8 * ppL3 + sp] = u[0];
+        p.src[16 * ppL3 + sp] = u[1];
+        p.src[24 * ppL3 + sp] = u[2];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Mq[k] = fma(e[k], w, Mq[k]);
+        dipole_apply(Mq, e, u);
+    }
+}
+
 template <bool ADJ>
 __device__ __forceinline__ void leaf_p2m(const DevPlan &p, const double *__restrict__ a0,
                                          const double *__restrict__ a1, int Qx, int Qy, int Qz, double *Mq)
@@ -1333,58 +1387,94 @@ __global__ __launch_bounds__(WG) void k_amr_leaf_moments(const DevPlan p, const 
     store_moments(p.lev[p.L], x, y, z, Mq, false);
 }
 
-// moments of the refined cells of level l: from the sources of leaf children
-// (P2M, staged for the leaf pass; p is the view of level l + 1) or by M2M
-// from the full moments of refined children
+// Sums v over each aligned group of S lanes (S a power of two) with a fixed
+// xor butterfly, for 8 lanes ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
+// every lane of a group ends with the same bits, since the partner lane adds
+// the same two values in swapped order.
+template <int S>
+__device__ __forceinline__ void lane_sum(double *v)
+{
+#pragma unroll
+    for (int off = 1; off < S; off <<= 1)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k] += __shfl_xor(v[k], off, 64);
+}
+
+// moments of the cells of the n refined sub-grids of level l from their
+// children: the M2M of the refined child sub-grid's full moments, or, when the
+// child sub-grid is a leaf, the P2M of its leaf cells, whose sources it stages
+// for the leaf pass (p is the view of level l + 1).  Eight lanes per cell,
+// lane b = child b; their shifted moments are summed by lane_sum<8>.
 template <bool ADJ>
 __global__ __launch_bounds__(WG) void k_amr_m2m(const DevPlan p, int l, const int32_t *__restrict__ nodes, int n,
                                                 const uint8_t *__restrict__ child_type, const double *__restrict__ a0,
                                                 const double *__restrict__ a1)
 {
     const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (t >= (int64_t)n * 512) return;
+    if (t >= (int64_t)n * 4096) return;          // whole waves: n * 4096 is a multiple of WG
+    const int64_t c = t >> 3;
+    const int b = (int)(t & 7);
     int x, y, z;
-    amr_cell(nodes[t >> 9], (int)(t & 511), x, y, z);
+    amr_cell(nodes[c >> 9], (int)(c & 511), x, y, z);
     const int64_t mc = (int64_t)2 << l;                   // sub-grids per axis one level down
     const uint8_t ct = child_type[((int64_t)(z >> 2) * mc + (y >> 2)) * mc + (x >> 2)];
     double Mq[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) Mq[c] = 0.0;
+    for (int k = 0; k < NC; ++k) Mq[k] = 0.0;
     if (ct == 1) {
-        leaf_p2m<ADJ>(p, a0, a1, x, y, z, Mq);
+        leaf_p2m_child<ADJ>(p, a0, a1, leaf_q(p, x, y, z), b, Mq);
     } else {
         const DevLevel &Dc = p.lev[l + 1];
         const int64_t pp = Dc.pp, pp3 = pp * pp * pp;
         const int64_t pad = ((int64_t)(z + Dc.hp) * pp + (y + Dc.hp)) * pp + (x + Dc.hp);
         const double hh = 0.5 * Dc.h;
-        for (int b = 0; b < 8; ++b) {
-            double Mc[NC], e[NC];
+        double Mc[NC], e[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) Mc[c] = Dc.M[(c * 8 + b) * pp3 + pad];
-            taylor((b & 1) ? -hh : hh, ((b >> 1) & 1) ? -hh : hh, (b >> 2) ? -hh : hh, e);   // e(z_cell - z_child)
-            m2m_apply(Mq, e, Mc);
-        }
+        for (int k = 0; k < NC; ++k) Mc[k] = Dc.M[(k * 8 + b) * pp3 + pad];
+        taylor((b & 1) ? -hh : hh, ((b >> 1) & 1) ? -hh : hh, (b >> 2) ? -hh : hh, e);   // e(z_cell - z_child)
+        m2m_apply(Mq, e, Mc);
     }
-    store_moments(p.lev[l], x, y, z, Mq, p.lev[l].M != nullptr, true);
+    lane_sum<8>(Mq);
+    if (b == 0) store_moments(p.lev[l], x, y, z, Mq, p.lev[l].M != nullptr, true);
 }
 
 // final local expansions of the cells of the n refined sub-grids of level l:
-// their M2L pieces plus the shift of the parent's (the same sums, in the same
-// order, as k_l2l_span)
+// their M2L pieces plus the shift of the parent's.  S lanes per cell: lane s
+// sums pieces s, s + S, ... in order, lane_sum<S> adds the lanes' sums.
+template <int S>
 __global__ __launch_bounds__(WG) void k_amr_l2l(const DevPlan p, int l, const int32_t *__restrict__ nodes, int n)
 {
     const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (t >= (int64_t)n * 512) return;
+    if (t >= (int64_t)n * 512 * S) return;       // whole waves: n * 512 * S is a multiple of WG
+    const int64_t cell = t / S;
+    const int ls = (int)(t % S);
     int cx, cy, cz;
-    amr_cell(nodes[t >> 9], (int)(t & 511), cx, cy, cz);
+    amr_cell(nodes[cell >> 9], (int)(cell & 511), cx, cy, cz);
     const DevLevel &D = p.lev[l];
     const int bs = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
-    const int64_t np = D.np, np3 = np * np * np;
+    const int64_t np = D.np, np3 = np * np * np, cs = 8 * np3;
     const int64_t q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
     double C[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) C[k] = 0.0;
-    add_pieces<4>(C, D.Cp + bs * np3 + q, 8 * np3, D.maxp);
+    const double *cp = D.Cp + bs * np3 + q;
+    int piece = ls;
+    for (; piece + S < D.maxp; piece += 2 * S) {      // two pieces' loads before their adds
+        double t0[NC], t1[NC];
+        const double *p0 = cp + piece * NC * cs, *p1 = cp + (piece + S) * NC * cs;
+        asm volatile("" : "+v"(p0), "+v"(p1));
+        const gdouble *g0 = (const gdouble *)p0, *g1 = (const gdouble *)p1;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) { t0[k] = g0[k * cs]; t1[k] = g1[k * cs]; }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) C[k] = (C[k] + t0[k]) + t1[k];
+    }
+    if (piece < D.maxp) {
+        const gdouble *g0 = (const gdouble *)(cp + piece * NC * cs);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) C[k] += g0[k * cs];
+    }
+    lane_sum<S>(C);
     if (l > 0) {
         const DevLevel &Dp = p.lev[l - 1];
         const int Rx = cx >> 1, Ry = cy >> 1, Rz = cz >> 1;
@@ -1398,8 +1488,10 @@ __global__ __launch_bounds__(WG) void k_amr_l2l(const DevPlan p, int l, const in
         taylor((cx & 1) ? hh : -hh, (cy & 1) ? hh : -hh, (cz & 1) ? hh : -hh, e);   // e(z_c - z_parent)
         l2l_apply(C, e, Cp);
     }
+    if (ls == 0) {
 #pragma unroll
-    for (int k = 0; k < NC; ++k) D.C[(k * 8 + bs) * np3 + q] = C[k];
+        for (int k = 0; k < NC; ++k) D.C[(k * 8 + bs) * np3 + q] = C[k];
+    }
 }
 
 // source plane value of cell (x, y, z) of a level whose planes are padded by
@@ -1887,7 +1979,7 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
                           const double *a0, const double *a1, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const dim3 grid(grid_for((int64_t)n * 512));
+    const dim3 grid(grid_for((int64_t)n * 4096));
     if (adj)
         hipLaunchKernelGGL(k_amr_m2m<true>, grid, dim3(WG), 0, s, v, l, nodes, n, child_type, a0, a1);
     else
@@ -1898,7 +1990,15 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_amr_l2l, dim3(grid_for((int64_t)n * 512)), dim3(WG), 0, s, p, l, nodes, n);
+    // lanes per cell from the level's pieces per cell: at most 4 pieces a lane
+    const int maxp = p.lev[l].maxp;
+    const int64_t cells = (int64_t)n * 512;
+    if (maxp > 16)
+        hipLaunchKernelGGL(k_amr_l2l<16>, dim3(grid_for(cells * 16)), dim3(WG), 0, s, p, l, nodes, n);
+    else if (maxp > 4)
+        hipLaunchKernelGGL(k_amr_l2l<4>, dim3(grid_for(cells * 4)), dim3(WG), 0, s, p, l, nodes, n);
+    else
+        hipLaunchKernelGGL(k_amr_l2l<1>, dim3(grid_for(cells)), dim3(WG), 0, s, p, l, nodes, n);
     return hipGetLastError();
 }
 
