@@ -1990,12 +1990,15 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    // lanes per cell from the level's pieces per cell: at most 4 pieces a lane
+    // lanes per cell from the level's pieces per cell: one piece a lane up to
+    // 16 pieces (these launches are short and wait on memory), 32 lanes beyond
     const int maxp = p.lev[l].maxp;
     const int64_t cells = (int64_t)n * 512;
     if (maxp > 16)
-        hipLaunchKernelGGL(k_amr_l2l<16>, dim3(grid_for(cells * 16)), dim3(WG), 0, s, p, l, nodes, n);
+        hipLaunchKernelGGL(k_amr_l2l<32>, dim3(grid_for(cells * 32)), dim3(WG), 0, s, p, l, nodes, n);
     else if (maxp > 4)
+        hipLaunchKernelGGL(k_amr_l2l<16>, dim3(grid_for(cells * 16)), dim3(WG), 0, s, p, l, nodes, n);
+    else if (maxp > 1)
         hipLaunchKernelGGL(k_amr_l2l<4>, dim3(grid_for(cells * 4)), dim3(WG), 0, s, p, l, nodes, n);
     else
         hipLaunchKernelGGL(k_amr_l2l<1>, dim3(grid_for(cells)), dim3(WG), 0, s, p, l, nodes, n);
