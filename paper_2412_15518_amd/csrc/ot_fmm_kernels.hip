@@ -1387,15 +1387,15 @@ __global__ __launch_bounds__(WG) void k_amr_leaf_moments(const DevPlan p, const 
     store_moments(p.lev[p.L], x, y, z, Mq, false);
 }
 
-// Sums v over each aligned group of S lanes (S a power of two) with a fixed
-// xor butterfly, for 8 lanes ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
-// every lane of a group ends with the same bits, since the partner lane adds
-// the same two values in swapped order.
-template <int S>
+// Sums v over the S lanes l0 + STRIDE j (j < S, S a power of two, l0 < STRIDE)
+// with a fixed xor butterfly, for 8 lanes ((v0 + v1) + (v2 + v3)) +
+// ((v4 + v5) + (v6 + v7)); every lane of a group ends with the same bits,
+// since the partner lane adds the same two values in swapped order.
+template <int S, int STRIDE = 1>
 __device__ __forceinline__ void lane_sum(double *v)
 {
 #pragma unroll
-    for (int off = 1; off < S; off <<= 1)
+    for (int off = STRIDE; off < S * STRIDE; off <<= 1)
 #pragma unroll
         for (int k = 0; k < NC; ++k) v[k] += __shfl_xor(v[k], off, 64);
 }
@@ -1439,15 +1439,19 @@ __global__ __launch_bounds__(WG) void k_amr_m2m(const DevPlan p, int l, const in
 }
 
 // final local expansions of the cells of the n refined sub-grids of level l:
-// their M2L pieces plus the shift of the parent's.  S lanes per cell: lane s
-// sums pieces s, s + S, ... in order, lane_sum<S> adds the lanes' sums.
+// their M2L pieces plus the shift of the parent's.  S lanes per cell: a wave
+// holds 64 / S consecutive cells, lane s * 64 / S + i sums pieces s, s + S, ...
+// of cell i in order (so that the lanes reading one piece read neighbouring
+// cells), and lane_sum adds the S lanes' sums.
 template <int S>
 __global__ __launch_bounds__(WG) void k_amr_l2l(const DevPlan p, int l, const int32_t *__restrict__ nodes, int n)
 {
+    constexpr int CPW = 64 / S;                  // cells per wave
     const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (t >= (int64_t)n * 512 * S) return;       // whole waves: n * 512 * S is a multiple of WG
-    const int64_t cell = t / S;
-    const int ls = (int)(t % S);
+    const int wl = (int)(t & 63);
+    const int64_t cell = (t >> 6) * CPW + wl % CPW;
+    const int ls = wl / CPW;
     int cx, cy, cz;
     amr_cell(nodes[cell >> 9], (int)(cell & 511), cx, cy, cz);
     const DevLevel &D = p.lev[l];
@@ -1474,7 +1478,7 @@ __global__ __launch_bounds__(WG) void k_amr_l2l(const DevPlan p, int l, const in
 #pragma unroll
         for (int k = 0; k < NC; ++k) C[k] += g0[k * cs];
     }
-    lane_sum<S>(C);
+    lane_sum<S, CPW>(C);
     if (l > 0) {
         const DevLevel &Dp = p.lev[l - 1];
         const int Rx = cx >> 1, Ry = cy >> 1, Rz = cz >> 1;
@@ -1990,16 +1994,15 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    // lanes per cell from the level's pieces per cell: one piece a lane up to
-    // 16 pieces (these launches are short and wait on memory), 32 lanes beyond
+    // lanes per cell from the level's pieces per cell: at most two pieces a
+    // lane up to 16 pieces (these launches are short and wait on memory), 32
+    // lanes beyond
     const int maxp = p.lev[l].maxp;
     const int64_t cells = (int64_t)n * 512;
     if (maxp > 16)
         hipLaunchKernelGGL(k_amr_l2l<32>, dim3(grid_for(cells * 32)), dim3(WG), 0, s, p, l, nodes, n);
-    else if (maxp > 4)
-        hipLaunchKernelGGL(k_amr_l2l<16>, dim3(grid_for(cells * 16)), dim3(WG), 0, s, p, l, nodes, n);
-    else if (maxp > 1)
-        hipLaunchKernelGGL(k_amr_l2l<4>, dim3(grid_for(cells * 4)), dim3(WG), 0, s, p, l, nodes, n);
+    else if (maxp > 2)
+        hipLaunchKernelGGL(k_amr_l2l<8>, dim3(grid_for(cells * 8)), dim3(WG), 0, s, p, l, nodes, n);
     else
         hipLaunchKernelGGL(k_amr_l2l<1>, dim3(grid_for(cells)), dim3(WG), 0, s, p, l, nodes, n);
     return hipGetLastError();
