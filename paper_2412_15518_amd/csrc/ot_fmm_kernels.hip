@@ -1994,17 +1994,15 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    // lanes per cell from the level's pieces per cell: at most two pieces a
-    // lane up to 16 pieces (these launches are short and wait on memory), 32
-    // lanes beyond
+    // lanes per cell from the level's pieces per cell: 8 (at most two pieces a
+    // lane up to 16 pieces; these launches are short and wait on memory), 32
+    // beyond
     const int maxp = p.lev[l].maxp;
     const int64_t cells = (int64_t)n * 512;
     if (maxp > 16)
         hipLaunchKernelGGL(k_amr_l2l<32>, dim3(grid_for(cells * 32)), dim3(WG), 0, s, p, l, nodes, n);
-    else if (maxp > 2)
-        hipLaunchKernelGGL(k_amr_l2l<8>, dim3(grid_for(cells * 8)), dim3(WG), 0, s, p, l, nodes, n);
     else
-        hipLaunchKernelGGL(k_amr_l2l<1>, dim3(grid_for(cells)), dim3(WG), 0, s, p, l, nodes, n);
+        hipLaunchKernelGGL(k_amr_l2l<8>, dim3(grid_for(cells * 8)), dim3(WG), 0, s, p, l, nodes, n);
     return hipGetLastError();
 }
 
