@@ -493,6 +493,7 @@ struct M2LSched {
     std::vector<M2LDesc> mdesc;
     std::vector<int32_t> ulist[MAX_LEVELS];
     int maxp[MAX_LEVELS] = {};
+    std::vector<uint16_t> npieces[MAX_LEVELS];     // per block: its pieces, 0 if no unit of it is computed
 };
 
 // Whether unit (block blk, parent offset P) of level l reads a cell of a
@@ -523,6 +524,7 @@ void build_m2l_schedule(ot_fmm_plan P, int G, const std::vector<int32_t> *live_n
     for (int l = 0; l < MAX_LEVELS; ++l) {
         S.maxp[l] = 0;
         S.ulist[l].clear();
+        S.npieces[l].clear();
     }
     if (L < 1) return;
     std::vector<std::vector<int64_t>> pos(L);     // each level's computed units, in order
@@ -586,6 +588,13 @@ void build_m2l_schedule(ot_fmm_plan P, int G, const std::vector<int32_t> *live_n
         for (int64_t blk = 0; blk < U[l] / nP; ++blk)
             maxp = std::max(maxp, run_of(blk * nP + nP - 1) - run_of(blk * nP) + 1);
         S.maxp[l] = maxp;
+        // a block's pieces are numbered from the run holding its first unit
+        std::vector<char> has((size_t)(U[l] / nP), 0);
+        for (int64_t u : pos[l]) has[(size_t)(u / nP)] = 1;
+        S.npieces[l].assign(has.size(), 0);
+        for (size_t blk = 0; blk < has.size(); ++blk)
+            if (has[blk])
+                S.npieces[l][blk] = (uint16_t)(run_of((int64_t)blk * nP + nP - 1) - run_of((int64_t)blk * nP) + 1);
     }
 }
 
@@ -922,6 +931,9 @@ int setup_amr_views(ot_fmm_plan P, int G)
         v.src = srcs[l];
         v.own_Cp = (l < L && cpB[l]) ? cpB[l] : nullptr;
         v.own_maxp = (l < L) ? S.maxp[l] : 0;
+        v.own_np = nullptr;
+        v.own_subgrid_blocks = (4 << l) >= 16 ? 1 : 0;      // the M2L's blocks at this level (amr_block)
+        if (v.own_Cp && (rc = dev_upload(P, &v.own_np, S.npieces[l]))) return rc;
         v.ntype_L = P->dev_ntype[l];
         v.leaf_subgrid_blocks = P->lsub[l];
         if ((rc = dev_upload(P, &v.blist, P->lblk[l]))) return rc;

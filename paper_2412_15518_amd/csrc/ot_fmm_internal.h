@@ -133,6 +133,8 @@ struct DevPlan {
     // the leaf fields above describe its leaves); the level arrays lev[] are
     // shared.  Uniform trees leave all of these null / 0.
     const double *own_Cp; int own_maxp;  // the leaf-sink M2L's pieces of this level (null if none)
+    const uint16_t *own_np;              // pieces per M2L block of this level (0: no unit computed)
+    int own_subgrid_blocks;              // those M2L blocks are sub-grids (1) or rows (0)
     const int32_t *blist; int nblist;   // blocks of the leaf pass holding a leaf sub-grid of this level
     const uint8_t *ntype_L;             // kinds of this level's sub-grids (0 none, 1 leaf, 2 refined)
     int leaf_subgrid_blocks;            // blocks of the leaf pass are sub-grids (block_shape)

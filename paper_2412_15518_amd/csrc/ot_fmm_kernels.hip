@@ -1541,10 +1541,14 @@ __global__ __launch_bounds__(CF_WAVES * 64) void k_amr_cf(const DevPlan p, doubl
 #pragma unroll
         for (int a = 0; a < NA; ++a) acc[b][a] = 0.0;
     if (live && p.own_Cp) {
-        // the pieces are dealt to the waves (piece k to wave k mod CF_WAVES)
+        // the pieces of Q's M2L block (as many as the block received) are
+        // dealt to the waves (piece k to wave k mod CF_WAVES)
         const int64_t nq = p.lev[p.L].np, nq3 = nq * nq * nq;
         const int64_t q = ((int64_t)Qz * nq + Qy) * nq + Qx;
-        for (int piece = wave; piece < p.own_maxp; piece += CF_WAVES) {
+        const Block mb = block_shape(npL, p.own_subgrid_blocks);
+        const int mbx = npL / mb.bx, mby = npL / mb.by;
+        const int npc = p.own_np[((Qz / mb.bz) * mby + Qy / mb.by) * mbx + Qx / mb.bx];
+        for (int piece = wave; piece < npc; piece += CF_WAVES) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const double *cp = p.own_Cp + ((int64_t)piece * NC * 8 + b) * nq3 + q;
