@@ -1768,9 +1768,9 @@ __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const doub
 // Pi of the cells of the deeper levels, organised like the M2L: a workgroup
 // of 8 waves owns a block of 64 parents (lane = parent) and wave w its sink
 // child w.  For each parent offset P the moments of the 8 source children of
-// the 64 parents Q + P are staged once in LDS (wave w loads child w's) for
-// all 8 waves, and the kernel row of a (P, b') pair, which depends only on
-// the offset 2P + b' - w, is the same for the whole wave.
+// the 64 parents Q + P are staged once in LDS (wave w loads child w's, one
+// offset ahead) for all 8 waves, and the kernel row of a (P, b') pair, which
+// depends only on the offset 2P + b' - w, is the same for the whole wave.
 constexpr int AM_WG = 512;
 __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, const double *__restrict__ KX,
                                                       double *__restrict__ Pi)
@@ -1796,12 +1796,22 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
 #pragma unroll
         for (int a = 0; a < NC; ++a) P3[j][a] = 0.0;
     constexpr AMTerms T = make_am_terms();
-    for (int i = 0; i < nP; ++i) {
+    // the moments of offset i + 1 are loaded into registers while offset i's
+    // products run, and stored to LDS at the top of the next step
+    double nx[NC];
+    auto load = [&](int i) {
         const char4 P = p.plist_near[i];
         const int64_t pad = ((int64_t)(Qz + P.z + D.hp) * pp + (Qy + P.y + D.hp)) * pp + (Qx + P.x + D.hp);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) tile[(w * NC + c) * 64 + lane] = D.M[(c * 8 + w) * pp3 + pad];
+        for (int c = 0; c < NC; ++c) nx[c] = D.M[(c * 8 + w) * pp3 + pad];
+    };
+    load(0);
+    for (int i = 0; i < nP; ++i) {
+        const char4 P = p.plist_near[i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) tile[(w * NC + c) * 64 + lane] = nx[c];
         __syncthreads();
+        if (i + 1 < nP) load(i + 1);
         for (int bp = 0; bp < 8; ++bp) {
             const int ox = 2 * P.x + (bp & 1) - (w & 1), oy = 2 * P.y + ((bp >> 1) & 1) - ((w >> 1) & 1),
                       oz = 2 * P.z + (bp >> 2) - (w >> 2);
