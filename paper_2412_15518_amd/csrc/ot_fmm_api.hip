@@ -1061,6 +1061,8 @@ int setup_device(ot_fmm_plan P)
         if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device)) != hipSuccess)
             return hip_fail(e, "hipDeviceGetAttribute");
         P->am_tiled = (size_t)lds >= AM_TILE_LDS ? 1 : 0;
+        const size_t nsplit = am_split_size(L);
+        if (P->am_tiled && nsplit && (rc = dev_alloc(P, &P->Pi_part, nsplit, false))) return rc;
     }
     // stencil chunks of the leaf passes: the smallest power of two that gives
     // a launch at least 16384 waves (four rounds of the 4096 wave slots the
@@ -1475,7 +1477,7 @@ int ot_fmm_am_correction(ot_fmm_plan P, const double *rho, double *t, void *hip_
     hipError_t e;
     if ((e = launch_upward_leaf(d, rho, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf");
     if ((e = launch_m2m_upper(d, s)) != hipSuccess) return hip_fail(e, "launch of the upper M2M spans");
-    if ((e = launch_am_correction(d, P->dev_KX, P->Pi, P->dev_Pi, t, P->am_tiled, s)) != hipSuccess)
+    if ((e = launch_am_correction(d, P->dev_KX, P->Pi, P->dev_Pi, P->Pi_part, t, P->am_tiled, s)) != hipSuccess)
         return hip_fail(e, "launch of the angular-momentum correction");
     return OT_FMM_OK;
 }

@@ -195,6 +195,7 @@ struct ot_fmm_plan_s {
     double *Pi[otfmm::MAX_LEVELS] = {};                // [3 * NC][8][np^3] per level
     double *const *dev_Pi = nullptr;
     int am_tiled = 0;                                  // the device gives a workgroup AM_TILE_LDS of LDS
+    double *Pi_part = nullptr;                         // partial Pi of the levels whose offsets are split
     const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
     const uint8_t *dev_ntype[otfmm::MAX_LEVELS] = {};
     std::vector<int32_t> ulist[otfmm::MAX_LEVELS];    // M2L units computed, per level
@@ -233,10 +234,34 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 // angular-momentum correction of a uniform plan whose levels keep full
 // moments (after its upward pass): Pi per level (Pi_host: the device pointers
 // of levels 0..L-1; Pi_dev: the same array in device memory), then t[3N]
+// (Pi_part: am_split_size(p.L) doubles, used where tiled)
 hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
-                                double *t, int tiled, hipStream_t s);
+                                double *Pi_part, double *t, int tiled, hipStream_t s);
 // LDS bytes of the tiled Pi kernel (tiled = 1 needs this much per workgroup)
 constexpr size_t AM_TILE_LDS = (size_t)8 * NC * 64 * sizeof(double);
+// The tiled Pi kernel at level l >= 1 splits its parent offsets into this
+// many parts, one workgroup each, where the level's 64-parent blocks alone
+// would leave most of the GPU idle (8 blocks at level 1, 64 at level 2); the
+// parts' sums are added in part order by a second kernel.
+inline int am_split(int l)
+{
+    const long nblk = (long)(4 << l) * (4 << l) * (4 << l) / 64;
+    if (nblk >= 256) return 1;
+    const long s = 256 / nblk;
+    return (int)(s > 32 ? 32 : s);
+}
+// doubles of the partial-sum buffer: the largest level that splits
+inline size_t am_split_size(int L)
+{
+    size_t m = 0;
+    for (int l = 1; l < L; ++l)
+        if (am_split(l) > 1) {
+            const size_t np3 = (size_t)(4 << l) * (4 << l) * (4 << l);
+            const size_t n = (size_t)am_split(l) * 3 * NC * 8 * np3;
+            m = n > m ? n : m;
+        }
+    return m;
+}
 //   final local expansions of the n refined sub-grids of level l (p: the plan)
 hipError_t launch_amr_l2l(const DevPlan &p, int l, const int32_t *nodes, int n, hipStream_t s);
 //   for the leaves of level v.L: their own level's M2L part (below the finest

@@ -1773,14 +1773,16 @@ __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const doub
 // depends only on the offset 2P + b' - w, is the same for the whole wave.
 constexpr int AM_WG = 512;
 __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, const double *__restrict__ KX,
-                                                      double *__restrict__ Pi)
+                                                      double *__restrict__ Pi, int split)
 {
     extern __shared__ double tile[];                   // [8 source children][NC][64]
     const DevLevel &D = p.lev[l];
     const int np = D.np;
     const Block bs = block_shape(np);
     const int nbx = np / bs.bx, nby = np / bs.by, nbz = np / bs.bz;
-    const int blk = blockIdx.x;
+    // split > 1: workgroup = (block, part), the part's offsets i0 .. i1 - 1,
+    // its sums written to partial buffer `part` (Pi then holds split buffers)
+    const int blk = blockIdx.x / split, part = blockIdx.x % split;
     if (blk >= nbx * nby * nbz) return;               // the whole workgroup
     const int lane = threadIdx.x & 63;
     const int w = uniform(threadIdx.x >> 6);           // sink child, and the source child this wave stages
@@ -1805,13 +1807,14 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
 #pragma unroll
         for (int c = 0; c < NC; ++c) nx[c] = D.M[(c * 8 + w) * pp3 + pad];
     };
-    load(0);
-    for (int i = 0; i < nP; ++i) {
+    const int i0 = part * nP / split, i1 = (part + 1) * nP / split;
+    load(i0);
+    for (int i = i0; i < i1; ++i) {
         const char4 P = p.plist_near[i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) tile[(w * NC + c) * 64 + lane] = nx[c];
         __syncthreads();
-        if (i + 1 < nP) load(i + 1);
+        if (i + 1 < i1) load(i + 1);
         for (int bp = 0; bp < 8; ++bp) {
             const int ox = 2 * P.x + (bp & 1) - (w & 1), oy = 2 * P.y + ((bp >> 1) & 1) - ((w >> 1) & 1),
                       oz = 2 * P.z + (bp >> 2) - (w >> 2);
@@ -1829,10 +1832,22 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
         __syncthreads();
     }
     const int64_t q = ((int64_t)Qz * np + Qy) * np + Qx;
+    double *out = Pi + (int64_t)part * 3 * NC * 8 * np3;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int a = 0; a < NC; ++a) Pi[((int64_t)(j * NC + a) * 8 + w) * np3 + q] = P3[j][a];
+        for (int a = 0; a < NC; ++a) out[((int64_t)(j * NC + a) * 8 + w) * np3 + q] = P3[j][a];
+}
+
+// Pi[e] = the split parts' sums of element e, added in part order
+__global__ __launch_bounds__(WG) void k_am_sum(const double *__restrict__ parts, int split, int64_t n,
+                                               double *__restrict__ Pi)
+{
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= n) return;
+    double s = parts[t];
+    for (int k = 1; k < split; ++k) s += parts[k * n + t];
+    Pi[t] = s;
 }
 
 // t at every leaf cell: the ancestors' Pi evaluated at the cell centre
@@ -2035,22 +2050,33 @@ hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, 
 namespace otfmm {
 
 hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
-                                double *t, int tiled, hipStream_t s)
+                                double *Pi_part, double *t, int tiled, hipStream_t s)
 {
     for (int l = 0; l < p.L; ++l) {
         const int64_t n = 8 << l;
-        // measured at 128^3: a wave per cell for the 512 and 4096 cells of
-        // levels 0 and 1 (81 and 176 us), a thread per cell at level 2 (0.70 ms;
-        // a wave per cell 1.25, tiled 0.96), the tiled form from level 3 on
-        // (1.58 ms against 2.6 with a thread per cell, which stays where the
-        // device's LDS is too small)
-        if (l <= 1)
+        // measured at 128^3: a wave per cell for the 512 cells of level 0
+        // (81 us); the tiled form from level 1 on, its offsets split over
+        // several workgroups at levels 1 and 2, which have only 8 and 64
+        // blocks.  Without the LDS for it: a wave per cell at level 1 (176
+        // us), a thread per cell below (0.70 ms at level 2, 2.6 at level 3).
+        if (l == 0 || (!tiled && l == 1)) {
             hipLaunchKernelGGL(k_am_pi<true>, dim3((unsigned)(n * n * n)), dim3(64), 0, s, p, l, KX, Pi_host[l]);
-        else if (l == 2 || !tiled)
+        } else if (!tiled) {
             hipLaunchKernelGGL(k_am_pi<false>, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
-        else
-            hipLaunchKernelGGL(k_am_pi_tile, dim3((unsigned)(n * n * n / 512)), dim3(AM_WG),
-                               AM_TILE_LDS, s, p, l, KX, Pi_host[l]);
+        } else {
+            const int split = am_split(l);
+            const unsigned nblk = (unsigned)(n * n * n / 512);
+            if (split == 1) {
+                hipLaunchKernelGGL(k_am_pi_tile, dim3(nblk), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, Pi_host[l], 1);
+            } else {
+                const int64_t ne = 3 * NC * 8 * (n * n * n / 8);
+                hipLaunchKernelGGL(k_am_pi_tile, dim3(nblk * split), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, Pi_part,
+                                   split);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_am_sum, dim3(grid_for(ne)), dim3(WG), 0, s, Pi_part, split, ne, Pi_host[l]);
+            }
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
