@@ -239,22 +239,22 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
                                 double *Pi_part, double *t, int tiled, hipStream_t s);
 // LDS bytes of the tiled Pi kernel (tiled = 1 needs this much per workgroup)
 constexpr size_t AM_TILE_LDS = (size_t)8 * NC * 64 * sizeof(double);
-// The tiled Pi kernel at level l >= 1 splits its parent offsets into this
-// many parts, one workgroup each, where the level's 64-parent blocks alone
-// would leave most of the GPU idle (8 blocks at level 1, 64 at level 2); the
-// parts' sums are added in part order by a second kernel.
+// The tiled Pi kernel splits the parent offsets of level l into this many
+// parts, one workgroup each, where the level's 64-parent blocks alone would
+// leave most of the GPU idle (1 block at level 0, 8 at level 1, 64 at level
+// 2); the parts' sums are added in part order by a second kernel, whose
+// chain of adds caps the parts at 64.
 inline int am_split(int l)
 {
     const long nblk = (long)(4 << l) * (4 << l) * (4 << l) / 64;
     if (nblk >= 256) return 1;
-    const long s = 256 / nblk;
-    return (int)(s > 32 ? 32 : s);
+    return 256 / nblk > 64 ? 64 : (int)(256 / nblk);
 }
 // doubles of the partial-sum buffer: the largest level that splits
 inline size_t am_split_size(int L)
 {
     size_t m = 0;
-    for (int l = 1; l < L; ++l)
+    for (int l = 0; l < L; ++l)
         if (am_split(l) > 1) {
             const size_t np3 = (size_t)(4 << l) * (4 << l) * (4 << l);
             const size_t n = (size_t)am_split(l) * 3 * NC * 8 * np3;

@@ -1789,7 +1789,8 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
     const int Qx = (blk % nbx) * bs.bx + lane % bs.bx;
     const int Qy = ((blk / nbx) % nby) * bs.by + (lane / bs.bx) % bs.by;
     const int Qz = (blk / (nbx * nby)) * bs.bz + lane / (bs.bx * bs.by);
-    const int nP = p.n_plist_near;
+    const int nP = l == 0 ? p.n_plist_cube : p.n_plist_near;      // level 0: the whole root cube
+    const char4 *plist = l == 0 ? p.plist_cube : p.plist_near;
     const int64_t pp = D.pp, pp3 = pp * pp * pp, np3 = (int64_t)np * np * np;
     const double *KXl = KX + (int64_t)l * OFF_N * 30;
     double P3[3][NC];
@@ -1802,7 +1803,7 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
     // products run, and stored to LDS at the top of the next step
     double nx[NC];
     auto load = [&](int i) {
-        const char4 P = p.plist_near[i];
+        const char4 P = plist[i];
         const int64_t pad = ((int64_t)(Qz + P.z + D.hp) * pp + (Qy + P.y + D.hp)) * pp + (Qx + P.x + D.hp);
 #pragma unroll
         for (int c = 0; c < NC; ++c) nx[c] = D.M[(c * 8 + w) * pp3 + pad];
@@ -1810,7 +1811,7 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
     const int i0 = part * nP / split, i1 = (part + 1) * nP / split;
     load(i0);
     for (int i = i0; i < i1; ++i) {
-        const char4 P = p.plist_near[i];
+        const char4 P = plist[i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) tile[(w * NC + c) * 64 + lane] = nx[c];
         __syncthreads();
@@ -1846,6 +1847,7 @@ __global__ __launch_bounds__(WG) void k_am_sum(const double *__restrict__ parts,
     const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (t >= n) return;
     double s = parts[t];
+#pragma unroll 8
     for (int k = 1; k < split; ++k) s += parts[k * n + t];
     Pi[t] = s;
 }
@@ -2054,12 +2056,11 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
 {
     for (int l = 0; l < p.L; ++l) {
         const int64_t n = 8 << l;
-        // measured at 128^3: a wave per cell for the 512 cells of level 0
-        // (81 us); the tiled form from level 1 on, its offsets split over
-        // several workgroups at levels 1 and 2, which have only 8 and 64
-        // blocks.  Without the LDS for it: a wave per cell at level 1 (176
+        // the tiled form, its offsets split over several workgroups at levels
+        // 0..2, which have only 1, 8 and 64 blocks.  Without the LDS for it
+        // (measured at 128^3): a wave per cell at levels 0 and 1 (81 and 176
         // us), a thread per cell below (0.70 ms at level 2, 2.6 at level 3).
-        if (l == 0 || (!tiled && l == 1)) {
+        if (!tiled && l <= 1) {
             hipLaunchKernelGGL(k_am_pi<true>, dim3((unsigned)(n * n * n)), dim3(64), 0, s, p, l, KX, Pi_host[l]);
         } else if (!tiled) {
             hipLaunchKernelGGL(k_am_pi<false>, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, KX, Pi_host[l]);
