@@ -1048,15 +1048,10 @@ int setup_device(ot_fmm_plan P)
     if (P->flags & OT_FMM_AM_CORRECTION) {
         am_table(P);
         if ((rc = dev_upload(P, &P->dev_KX, P->KX))) return rc;
-        std::vector<double *> pis(std::max(L, 1), nullptr);
         for (int l = 0; l < L; ++l) {
             const size_t np3 = (size_t)d.lev[l].np * d.lev[l].np * d.lev[l].np;
             if ((rc = dev_alloc(P, &P->Pi[l], (size_t)3 * NC * 8 * np3, true))) return rc;
-            pis[l] = P->Pi[l];
         }
-        double *const *dpi = nullptr;                 // the per-level pointers, in device memory
-        if ((rc = dev_upload(P, &dpi, pis))) return rc;
-        P->dev_Pi = dpi;
         int lds = 0;
         if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device)) != hipSuccess)
             return hip_fail(e, "hipDeviceGetAttribute");
@@ -1477,7 +1472,7 @@ int ot_fmm_am_correction(ot_fmm_plan P, const double *rho, double *t, void *hip_
     hipError_t e;
     if ((e = launch_upward_leaf(d, rho, s)) != hipSuccess) return hip_fail(e, "launch upward_leaf");
     if ((e = launch_m2m_upper(d, s)) != hipSuccess) return hip_fail(e, "launch of the upper M2M spans");
-    if ((e = launch_am_correction(d, P->dev_KX, P->Pi, P->dev_Pi, P->Pi_part, t, P->am_tiled, s)) != hipSuccess)
+    if ((e = launch_am_correction(d, P->dev_KX, P->Pi, P->Pi_part, t, P->am_tiled, s)) != hipSuccess)
         return hip_fail(e, "launch of the angular-momentum correction");
     return OT_FMM_OK;
 }

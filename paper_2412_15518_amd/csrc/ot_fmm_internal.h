@@ -193,7 +193,6 @@ struct ot_fmm_plan_s {
     std::vector<double> KX;                            // [L][OFF_N][10][3]
     const double *dev_KX = nullptr;
     double *Pi[otfmm::MAX_LEVELS] = {};                // [3 * NC][8][np^3] per level
-    double *const *dev_Pi = nullptr;
     int am_tiled = 0;                                  // the device gives a workgroup AM_TILE_LDS of LDS
     double *Pi_part = nullptr;                         // partial Pi of the levels whose offsets are split
     const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
@@ -233,10 +232,10 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
                           const double *a0, const double *a1, hipStream_t s);
 // angular-momentum correction of a uniform plan whose levels keep full
 // moments (after its upward pass): Pi per level (Pi_host: the device pointers
-// of levels 0..L-1; Pi_dev: the same array in device memory), then t[3N]
+// of levels 0..L-1), each level's then gaining its parent's, then t[3N]
 // (Pi_part: am_split_size(p.L) doubles, used where tiled)
-hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
-                                double *Pi_part, double *t, int tiled, hipStream_t s);
+hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *Pi_part,
+                                double *t, int tiled, hipStream_t s);
 // LDS bytes of the tiled Pi kernel (tiled = 1 needs this much per workgroup)
 constexpr size_t AM_TILE_LDS = (size_t)8 * NC * 64 * sizeof(double);
 // The tiled Pi kernel splits the parent offsets of level l into this many

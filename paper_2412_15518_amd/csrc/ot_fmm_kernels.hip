@@ -1773,7 +1773,8 @@ __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const doub
 // depends only on the offset 2P + b' - w, is the same for the whole wave.
 constexpr int AM_WG = 512;
 __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, const double *__restrict__ KX,
-                                                      double *__restrict__ Pi, int split)
+                                                      double *__restrict__ Pi, int split,
+                                                      const double *__restrict__ Pup)
 {
     extern __shared__ double tile[];                   // [8 source children][NC][64]
     const DevLevel &D = p.lev[l];
@@ -1832,6 +1833,23 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
         }
         __syncthreads();
     }
+    if (Pup) {
+        // split == 1, l > 0: fold in the parent's Pi (cell 2Q + w's parent is
+        // Q), as k_am_down does
+        const int bR = (Qx & 1) + 2 * (Qy & 1) + 4 * (Qz & 1);
+        const int64_t npp = p.lev[l - 1].np, npp3 = npp * npp * npp;
+        const int64_t qR = ((int64_t)(Qz >> 1) * npp + (Qy >> 1)) * npp + (Qx >> 1);
+        double e[NC];
+        const double hh = 0.5 * D.h;
+        taylor((w & 1) ? hh : -hh, ((w >> 1) & 1) ? hh : -hh, (w >> 2) ? hh : -hh, e);   // e(z_c - z_Q)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double Cp[NC];
+#pragma unroll
+            for (int a = 0; a < NC; ++a) Cp[a] = Pup[((int64_t)(j * NC + a) * 8 + bR) * npp3 + qR];
+            l2l_apply(P3[j], e, Cp);
+        }
+    }
     const int64_t q = ((int64_t)Qz * np + Qy) * np + Qx;
     double *out = Pi + (int64_t)part * 3 * NC * 8 * np3;
 #pragma unroll
@@ -1852,17 +1870,59 @@ __global__ __launch_bounds__(WG) void k_am_sum(const double *__restrict__ parts,
     Pi[t] = s;
 }
 
-// t at every leaf cell: the ancestors' Pi evaluated at the cell centre
-__global__ __launch_bounds__(WG) void k_am_leaf(const DevPlan p, double *const *__restrict__ Pi, double *__restrict__ tout)
+// Pi of level l gains its parent's, re-expanded about the cell's centre (the
+// L2L shift of each of the 3 components), so that the Pi of level L-1 holds
+// the whole sum over the ancestors.  One thread per cell of level l.
+__global__ __launch_bounds__(WG) void k_am_down(const DevPlan p, int l, const double *__restrict__ Pup,
+                                                double *__restrict__ Pi)
 {
-    const int n = 8 << p.L;
+    const DevLevel &D = p.lev[l], &Dp = p.lev[l - 1];
+    const int n = 2 * D.np;
     const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (t >= (int64_t)n * n * n) return;
     const int cx = (int)(t % n), cy = (int)((t / n) % n), cz = (int)(t / ((int64_t)n * n));
+    const int b = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+    const int64_t np = D.np, np3 = np * np * np;
+    const int64_t q = ((int64_t)(cz >> 1) * np + (cy >> 1)) * np + (cx >> 1);
+    const int Rx = cx >> 1, Ry = cy >> 1, Rz = cz >> 1;
+    const int bR = (Rx & 1) + 2 * (Ry & 1) + 4 * (Rz & 1);
+    const int64_t npp = Dp.np, npp3 = npp * npp * npp;
+    const int64_t qR = ((int64_t)(Rz >> 1) * npp + (Ry >> 1)) * npp + (Rx >> 1);
+    double e[NC];
+    const double hh = 0.5 * D.h;
+    taylor((cx & 1) ? hh : -hh, (cy & 1) ? hh : -hh, (cz & 1) ? hh : -hh, e);   // e(z_c - z_parent)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double C[NC], Cp[NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            C[a] = Pi[((int64_t)(j * NC + a) * 8 + b) * np3 + q];
+            Cp[a] = Pup[((int64_t)(j * NC + a) * 8 + bR) * npp3 + qR];
+        }
+        l2l_apply(C, e, Cp);
+#pragma unroll
+        for (int a = 0; a < NC; ++a) Pi[((int64_t)(j * NC + a) * 8 + b) * np3 + q] = C[a];
+    }
+}
+
+// t at every leaf cell: the Pi of its level-(L-1) ancestor, which holds the
+// shifted sum over all its ancestors, evaluated at the cell centre.  A
+// workgroup takes an 8 x 8 x 4 brick of leaf cells, a wave one 8 x 8 layer of
+// it (one sub-grid's).
+__global__ __launch_bounds__(WG) void k_am_leaf(const DevPlan p, const double *__restrict__ Pi,
+                                                double *__restrict__ tout)
+{
+    static_assert(WG == 256, "an 8 x 8 x 4 brick per workgroup");
+    const int n = 8 << p.L;
+    const int nbx = n / 8, nby = n / 8;
+    const int brick = blockIdx.x;
+    if (brick >= nbx * nby * (n / 4)) return;
+    const int cx = (brick % nbx) * 8 + (threadIdx.x & 7), cy = ((brick / nbx) % nby) * 8 + ((threadIdx.x >> 3) & 7),
+              cz = (brick / (nbx * nby)) * 4 + (threadIdx.x >> 6);
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int l = 0; l < p.L; ++l) {
-        const int sh = p.L - l;
-        const int ax = cx >> sh, ay = cy >> sh, az = cz >> sh;
+    if (p.L > 0) {
+        const int l = p.L - 1;
+        const int ax = cx >> 1, ay = cy >> 1, az = cz >> 1;
         const DevLevel &D = p.lev[l];
         // leaf centre minus the ancestor's centre
         const double x = (cx + 0.5) * p.hleaf - (ax + 0.5) * D.h, y = (cy + 0.5) * p.hleaf - (ay + 0.5) * D.h,
@@ -1872,11 +1932,10 @@ __global__ __launch_bounds__(WG) void k_am_leaf(const DevPlan p, double *const *
         const int64_t np = D.np, np3 = np * np * np;
         const int64_t q = ((int64_t)(az >> 1) * np + (ay >> 1)) * np + (ax >> 1);
         const int b = (ax & 1) + 2 * (ay & 1) + 4 * (az & 1);
-        const double *Pl = Pi[l];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int a = 0; a < NC; ++a) acc[j] = fma(e[a], Pl[((int64_t)(j * NC + a) * 8 + b) * np3 + q], acc[j]);
+            for (int a = 0; a < NC; ++a) acc[j] = fma(e[a], Pi[((int64_t)(j * NC + a) * 8 + b) * np3 + q], acc[j]);
     }
     const int64_t slot = p.leaf_slot[((int64_t)(cz >> 3) * p.sL + (cy >> 3)) * p.sL + (cx >> 3)];
     const int64_t idx = slot * 512 + ((cz & 7) * 8 + (cy & 7)) * 8 + (cx & 7);
@@ -2051,8 +2110,8 @@ hipError_t launch_amr_cf(const DevPlan &v, int adj, double *out0, double *out1, 
 
 namespace otfmm {
 
-hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *const *Pi_dev,
-                                double *Pi_part, double *t, int tiled, hipStream_t s)
+hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *Pi_part,
+                                double *t, int tiled, hipStream_t s)
 {
     for (int l = 0; l < p.L; ++l) {
         const int64_t n = 8 << l;
@@ -2068,21 +2127,29 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
             const int split = am_split(l);
             const unsigned nblk = (unsigned)(n * n * n / 512);
             if (split == 1) {
-                hipLaunchKernelGGL(k_am_pi_tile, dim3(nblk), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, Pi_host[l], 1);
+                // the parent's Pi folded in by the same launch
+                hipLaunchKernelGGL(k_am_pi_tile, dim3(nblk), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, Pi_host[l], 1,
+                                   l > 0 ? (const double *)Pi_host[l - 1] : nullptr);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                continue;
             } else {
                 const int64_t ne = 3 * NC * 8 * (n * n * n / 8);
                 hipLaunchKernelGGL(k_am_pi_tile, dim3(nblk * split), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, Pi_part,
-                                   split);
+                                   split, (const double *)nullptr);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
                 hipLaunchKernelGGL(k_am_sum, dim3(grid_for(ne)), dim3(WG), 0, s, Pi_part, split, ne, Pi_host[l]);
             }
         }
+        if (l > 0)                                 // fold in the ancestors' (final above level l)
+            hipLaunchKernelGGL(k_am_down, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, l, Pi_host[l - 1], Pi_host[l]);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     const int64_t n = 8 << p.L;
-    hipLaunchKernelGGL(k_am_leaf, dim3(grid_for(n * n * n)), dim3(WG), 0, s, p, Pi_dev, t);
+    hipLaunchKernelGGL(k_am_leaf, dim3((unsigned)(n * n * n / 256)), dim3(WG), 0, s, p,
+                       p.L > 0 ? Pi_host[p.L - 1] : nullptr, t);
     return hipGetLastError();
 }
 
