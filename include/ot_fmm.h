@@ -90,7 +90,9 @@ extern "C" {
                                         calls repeat bit for bit. */
 #define OT_FMM_AM_CORRECTION (1u << 3) /* keep what ot_fmm_am_correction needs
                                         (full moments at every level, order-4
-                                        kernel tables); uniform trees only */
+                                        kernel tables, per-level torque
+                                        polynomials and a partial-sum buffer of
+                                        at most 63 MB); uniform trees only */
 
 typedef struct ot_fmm_plan_s *ot_fmm_plan;   /* opaque */
 
