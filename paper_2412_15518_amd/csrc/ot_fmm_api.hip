@@ -1055,7 +1055,7 @@ int setup_device(ot_fmm_plan P)
         int lds = 0;
         if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device)) != hipSuccess)
             return hip_fail(e, "hipDeviceGetAttribute");
-        P->am_tiled = (size_t)lds >= AM_TILE_LDS ? 1 : 0;
+        P->am_tiled = (size_t)lds >= 2 * AM_TILE_LDS ? 2 : (size_t)lds >= AM_TILE_LDS ? 1 : 0;
         const size_t nsplit = am_split_size(L);
         if (P->am_tiled && nsplit && (rc = dev_alloc(P, &P->Pi_part, nsplit, false))) return rc;
     }

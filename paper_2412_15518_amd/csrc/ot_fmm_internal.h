@@ -193,7 +193,7 @@ struct ot_fmm_plan_s {
     std::vector<double> KX;                            // [L][OFF_N][10][3]
     const double *dev_KX = nullptr;
     double *Pi[otfmm::MAX_LEVELS] = {};                // [3 * NC][8][np^3] per level
-    int am_tiled = 0;                                  // the device gives a workgroup AM_TILE_LDS of LDS
+    int am_tiled = 0;                                  // the device gives a workgroup 2 AM_TILE_LDS (2), AM_TILE_LDS (1) of LDS
     double *Pi_part = nullptr;                         // partial Pi of the levels whose offsets are split
     const int32_t *dev_lnodes[otfmm::MAX_LEVELS] = {}, *dev_rnodes[otfmm::MAX_LEVELS] = {};
     const uint8_t *dev_ntype[otfmm::MAX_LEVELS] = {};
@@ -236,7 +236,8 @@ hipError_t launch_amr_m2m(const DevPlan &v, int adj, int l, const int32_t *nodes
 // (Pi_part: am_split_size(p.L) doubles, used where tiled)
 hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *const *Pi_host, double *Pi_part,
                                 double *t, int tiled, hipStream_t s);
-// LDS bytes of the tiled Pi kernel (tiled = 1 needs this much per workgroup)
+// LDS bytes of one staging buffer of the tiled Pi kernel (tiled = 1 needs this
+// much per workgroup, tiled = 2 twice as much)
 constexpr size_t AM_TILE_LDS = (size_t)8 * NC * 64 * sizeof(double);
 // The tiled Pi kernel splits the parent offsets of level l into this many
 // parts, one workgroup each, where the level's 64-parent blocks alone would

@@ -1772,11 +1772,16 @@ __global__ __launch_bounds__(WG) void k_am_pi(const DevPlan p, int l, const doub
 // offset ahead) for all 8 waves, and the kernel row of a (P, b') pair, which
 // depends only on the offset 2P + b' - w, is the same for the whole wave.
 constexpr int AM_WG = 512;
+// NBUF = 2: two staging buffers (twice the LDS), used by alternate offsets,
+// so one barrier per offset suffices: a wave that stores into a buffer has
+// passed the barrier that every wave reaches only after its products from
+// that buffer two offsets before.
+template <int NBUF>
 __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, const double *__restrict__ KX,
                                                       double *__restrict__ Pi, int split,
                                                       const double *__restrict__ Pup)
 {
-    extern __shared__ double tile[];                   // [8 source children][NC][64]
+    extern __shared__ double tiles[];                  // NBUF x [8 source children][NC][64]
     const DevLevel &D = p.lev[l];
     const int np = D.np;
     const Block bs = block_shape(np);
@@ -1813,6 +1818,7 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
     load(i0);
     for (int i = i0; i < i1; ++i) {
         const char4 P = plist[i];
+        double *tile = tiles + (NBUF == 2 ? ((i - i0) & 1) * (8 * NC * 64) : 0);
 #pragma unroll
         for (int c = 0; c < NC; ++c) tile[(w * NC + c) * 64 + lane] = nx[c];
         __syncthreads();
@@ -1831,7 +1837,7 @@ __global__ __launch_bounds__(AM_WG) void k_am_pi_tile(const DevPlan p, int l, co
                 for (int j = 0; j < 3; ++j)
                     P3[j][T.t[q].a] = fma(K[3 * (T.t[q].c - 10) + j], M[T.t[q].b], P3[j][T.t[q].a]);
         }
-        __syncthreads();
+        if (NBUF == 1) __syncthreads();
     }
     if (Pup) {
         // split == 1, l > 0: fold in the parent's Pi (cell 2Q + w's parent is
@@ -2126,17 +2132,24 @@ hipError_t launch_am_correction(const DevPlan &p, const double *KX, double *cons
         } else {
             const int split = am_split(l);
             const unsigned nblk = (unsigned)(n * n * n / 512);
+            // tiled = 2: the device gives a workgroup LDS for two staging buffers
+            auto tile = [&](unsigned grid, double *out, int parts, const double *up) {
+                if (tiled == 2)
+                    hipLaunchKernelGGL(k_am_pi_tile<2>, dim3(grid), dim3(AM_WG), 2 * AM_TILE_LDS, s, p, l, KX, out,
+                                       parts, up);
+                else
+                    hipLaunchKernelGGL(k_am_pi_tile<1>, dim3(grid), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, out, parts,
+                                       up);
+            };
             if (split == 1) {
                 // the parent's Pi folded in by the same launch
-                hipLaunchKernelGGL(k_am_pi_tile, dim3(nblk), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, Pi_host[l], 1,
-                                   l > 0 ? (const double *)Pi_host[l - 1] : nullptr);
+                tile(nblk, Pi_host[l], 1, l > 0 ? (const double *)Pi_host[l - 1] : nullptr);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
                 continue;
             } else {
                 const int64_t ne = 3 * NC * 8 * (n * n * n / 8);
-                hipLaunchKernelGGL(k_am_pi_tile, dim3(nblk * split), dim3(AM_WG), AM_TILE_LDS, s, p, l, KX, Pi_part,
-                                   split, (const double *)nullptr);
+                tile(nblk * split, Pi_part, split, nullptr);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
                 hipLaunchKernelGGL(k_am_sum, dim3(grid_for(ne)), dim3(WG), 0, s, Pi_part, split, ne, Pi_host[l]);
