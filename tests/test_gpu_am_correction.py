@@ -97,3 +97,30 @@ def test_full_size_sampled_and_conservation():
     spin = (m[None] * t.reshape(3, -1)).T
     say("orbital torque", orb.sum(0), "with the correction", orb.sum(0) + spin.sum(0))
     assert np.abs(orb.sum(0) + spin.sum(0)).max() / np.abs(orb).sum() < 1e-12
+
+
+def test_depth3_sampled_and_conservation():
+    """64^3, random node order: every Pi level is one whose parent offsets the
+    tiled kernel splits over several workgroups (levels 0..2), each folded
+    into its children's; sampled cells against the oracle, and the exact
+    torque balance with the GPU forward."""
+    lay = W.uniform_layout(3, order="random", seed=36)
+    rho = W.random_density(64, 37, "signed")
+    say("am correction, depth 3")
+    plan = fmm.Plan(lay, am_correction=True)
+    rd = torch.from_numpy(lay.dense_to_layout(rho)).cuda()
+    t = plan.am_correction(rd)
+    phi, g = plan.forward(rd)
+    torch.cuda.synchronize()
+    t = lay.layout_to_dense(t.cpu().numpy())
+    g = lay.layout_to_dense(g.cpu().numpy())
+    sk = np.random.default_rng(38).choice(64 ** 3, 256, replace=False)
+    to = O.am_correction(rho, sinks=sk)
+    assert normwise_vec(t.reshape(3, -1)[:, sk], to) < TOL
+    c = np.arange(64) + 0.5
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    X = np.stack([x, y, z]).reshape(3, -1).T
+    m = rho.reshape(-1)
+    orb = np.cross(X, (m[None] * g.reshape(3, -1)).T)
+    spin = (m[None] * t.reshape(3, -1)).T
+    assert np.abs(orb.sum(0) + spin.sum(0)).max() / np.abs(orb).sum() < 1e-12
